@@ -1,0 +1,483 @@
+"""Pins of the FP64 oracle against facts fixed by the thesis and by mathematics.
+
+Each test checks the oracle against something other than itself: values the
+thesis prints (tests/golden), textbook weights, closed forms (discrete plane
+wave, Green's function), invariants (energy, reciprocity, adjoint identity,
+polynomial exactness) or brute-force finite differences.  A plausible slip in
+the oracle (a dropped term, a wrong sign or index, a transposed operand)
+fails at least one of them.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *v = line.split()
+            out[k] = v
+    return out
+
+
+# ---------------------------------------------------------------- weights (O3)
+TEXTBOOK = {  # Fornberg (1988), centred second derivative, maximal order
+    2: ["-2", "1"],
+    4: ["-5/2", "4/3", "-1/12"],
+    6: ["-49/18", "3/2", "-3/20", "1/90"],
+    8: ["-205/72", "8/5", "-1/5", "8/315", "-1/560"],
+}
+
+
+@pytest.mark.parametrize("so", sorted(TEXTBOOK))
+def test_weights_textbook(so):
+    assert oracle.fd_weights_exact(so) == [Fraction(x) for x in TEXTBOOK[so]]
+
+
+def test_weights_match_printed_diffusion_kernel():
+    """Section 3.2.2 / 5.1.5 print the so-2 diffusion kernel: nu*c_0 = -1.0,
+    nu*c_1 = 0.5 with nu = 0.5."""
+    g = _golden("diffusion_so2_kernel.txt")
+    nu = float(g["nu"][0])
+    c = oracle.fd_weights(2)
+    assert nu * c[0] == float(g["centre"][0])
+    assert nu * c[1] == float(g["offset1"][0])
+
+
+@pytest.mark.parametrize("so", range(2, 17, 2))
+def test_weights_polynomial_order(so):
+    """Exact on x^k for k <= so+1, not exact for k = so+2 (maximal order)."""
+    c = oracle.fd_weights_exact(so)
+    r = so // 2
+
+    def d2_at0(k):  # stencil applied to x^k at x = 0, h = 1
+        s = c[0] * (1 if k == 0 else 0)
+        for j in range(1, r + 1):
+            s += c[j] * (Fraction(j) ** k + Fraction(-j) ** k)
+        return s
+
+    for k in range(0, so + 2):
+        assert d2_at0(k) == (2 if k == 2 else 0), (so, k)
+    assert d2_at0(so + 2) != 0
+
+
+# ---------------------------------------------------------- Laplacian (O4)
+def test_stencil_point_set_so2():
+    """A unit impulse touches exactly the 5-point star printed for so 2 in
+    Section 3.3.3 (s2d_ut0_5pt)."""
+    gold = _golden("diffusion_so2_kernel.txt")
+    want = {tuple(int(x) for x in p.split(",")) for p in gold["points"]}
+    g = oracle.Grid((9, 9), (1.0, 1.0), (0.0, 0.0), 2)
+    u = np.zeros(g.array_shape)
+    u[4, 4] = 1.0
+    lap = oracle.laplacian(g, u)
+    got = {(int(ix) - 4, int(iz) - 4) for iz, ix in zip(*np.nonzero(lap))}
+    assert got == want
+
+
+def test_halo_width_so4():
+    gold = _golden("halo_so4.txt")
+    so = int(gold["space_order"][0])
+    g = oracle.Grid((15, 15), (1.0, 1.0), (0.0, 0.0), so)
+    u = np.zeros(g.array_shape)
+    u[7, 7] = 1.0
+    lap = oracle.laplacian(g, u)
+    iz, ix = np.nonzero(lap)
+    assert ix.min() - 7 == int(gold["d_m"][0]) and ix.max() - 7 == int(gold["d_p"][0])
+    assert iz.min() - 7 == int(gold["d_m"][1]) and iz.max() - 7 == int(gold["d_p"][1])
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 16])
+def test_laplacian_polynomial_exact(so):
+    """Away from the faces the operator is exact on x^(so+1) + y^2 z^2 +
+    z^(so+1) (anisotropic spacing)."""
+    g = oracle.Grid((2 * so + 6, so + 7, 2 * so + 5), (0.5, 0.25, 0.75), (0.0, 0.0, 0.0), so)
+    nz, ny, nx = g.array_shape
+    z, y, x = np.meshgrid(np.arange(nz) * 0.75, np.arange(ny) * 0.25, np.arange(nx) * 0.5, indexing="ij")
+    x0, y0, z0 = x - x.mean(), y - y.mean(), z - z.mean()
+    k = so + 1
+    u = x0 ** k + y0 ** 2 * z0 ** 2 + z0 ** k
+    exact = k * (k - 1) * x0 ** (k - 2) + 2 * z0 ** 2 + 2 * y0 ** 2 + k * (k - 1) * z0 ** (k - 2)
+    lap = oracle.laplacian(g, u)
+    r = g.radius
+    sl = (slice(r, -r), slice(r, -r), slice(r, -r))
+    assert np.max(np.abs(lap[sl] - exact[sl])) <= 1e-9 * np.max(np.abs(exact[sl])) + 1e-9
+
+
+@pytest.mark.parametrize("so", range(2, 17, 2))
+def test_laplacian_convergence_order(so):
+    """Observed order of Lap_h on a smooth field equals the space order
+    (h = 1/24 -> 1/48, k h <= 0.92; the pre-asymptotic shortfall stays
+    below 0.5 up to so 16)."""
+    errs = []
+    for n in (24, 48):
+        h = 1.0 / n
+        g = oracle.Grid((n + 1, n + 1), (h, h), (0.0, 0.0), so)
+        x = np.arange(n + 1) * h
+        kx, kz = 22.0, 17.0
+        u = np.sin(kx * x[None, :] + 0.3) * np.cos(kz * x[:, None] + 0.1)
+        ex = -(kx ** 2 + kz ** 2) * u
+        lap = oracle.laplacian(g, u)
+        c = n // 2
+        errs.append(abs(lap[c, c] - ex[c, c]))
+    order = math.log2(errs[0] / errs[1])
+    assert abs(order - so) < 0.5, (so, order, errs)
+
+
+def test_laplacian_symmetric_zero_extension():
+    """<a, L b> = <L a, b> (zero extension makes L symmetric) and a corner
+    impulse keeps only in-grid stencil points."""
+    g = oracle.Grid((11, 9, 10), (1.0, 2.0, 1.5), (0.0, 0.0, 0.0), 6)
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(g.array_shape)
+    b = rng.standard_normal(g.array_shape)
+    la, lb = oracle.laplacian(g, a), oracle.laplacian(g, b)
+    assert abs(np.sum(a * lb) - np.sum(la * b)) <= 1e-12 * np.sum(np.abs(a * lb))
+    u = np.zeros(g.array_shape)
+    u[0, 0, 0] = 1.0
+    lap = oracle.laplacian(g, u)
+    c = oracle.fd_weights(6)
+    assert lap[0, 0, 0] == pytest.approx(c[0] * (1 + 1 / 4 + 1 / 2.25))
+    for j in range(1, 4):
+        assert lap[0, 0, j] == pytest.approx(c[j])
+        assert lap[0, j, 0] == pytest.approx(c[j] / 4)
+        assert lap[j, 0, 0] == pytest.approx(c[j] / 2.25)
+    assert np.count_nonzero(lap) == 1 + 3 * 3
+
+
+# ---------------------------------------------------------- sparse (O8, O9)
+def test_sparse_weights_exact_on_multilinear_fields():
+    g = oracle.Grid((12, 10, 9), (10.0, 7.0, 5.0), (3.0, -2.0, 1.0), 4, nbl=3)
+    rng = np.random.default_rng(1)
+    pts = np.column_stack([3.0 + rng.uniform(0, 110, 20), -2.0 + rng.uniform(0, 63, 20),
+                           1.0 + rng.uniform(0, 40, 20)])
+    pts[0] = (3.0 + 110.0, -2.0 + 63.0, 1.0 + 40.0)        # last grid line: cell N-2, p = 1
+    idx, w = oracle.sparse_weights(g, pts)
+    assert np.allclose(w.sum(axis=1), 1.0) and (w >= -1e-15).all()
+    nz, ny, nx = g.array_shape
+    z, y, x = np.meshgrid(1.0 + (np.arange(nz) - 3) * 5.0, -2.0 + (np.arange(ny) - 3) * 7.0,
+                          3.0 + (np.arange(nx) - 3) * 10.0, indexing="ij")
+    f = 1.5 + 0.2 * x - 0.7 * y + 0.3 * z + 0.01 * x * y - 0.02 * y * z + 0.003 * x * y * z
+    vals = (w * f.ravel()[idx]).sum(axis=1)
+    P = pts
+    fx = 1.5 + 0.2 * P[:, 0] - 0.7 * P[:, 1] + 0.3 * P[:, 2] + 0.01 * P[:, 0] * P[:, 1] \
+        - 0.02 * P[:, 1] * P[:, 2] + 0.003 * P[:, 0] * P[:, 1] * P[:, 2]
+    assert np.allclose(vals, fx, rtol=1e-12, atol=1e-10)
+
+
+def test_sparse_weights_on_grid_and_outside():
+    g = oracle.Grid((6, 5), (10.0, 10.0), (0.0, 0.0), 2, nbl=2)
+    idx, w = oracle.sparse_weights(g, [(20.0, 30.0)])
+    k = np.argmax(w[0])
+    assert w[0, k] == 1.0 and np.count_nonzero(w[0]) == 1
+    assert idx[0, k] == (2 + 2) + (3 + 2) * 10
+    with pytest.raises(ValueError):
+        oracle.sparse_weights(g, [(50.0 + 1e-9, 0.0)])
+    with pytest.raises(ValueError):
+        oracle.sparse_weights(g, [(0.0, -1e-9)])
+
+
+# ---------------------------------------------------------- damping (O5)
+def test_damping_profile():
+    g = oracle.Grid((10, 8, 6), (10.0, 10.0, 10.0), (0.0, 0.0, 0.0), 4, nbl=4)
+    s = oracle.damping(g, 2.0)
+    assert s.shape == (14, 16, 18)
+    assert np.all(s[4:10, 4:12, 4:14] == 0.0)
+    assert s[0, 0, 0] == pytest.approx(3 * 2.0)                      # every axis at d = nbl
+    assert s[4, 4, 0] == pytest.approx(2.0) and s[4, 4, 17] == pytest.approx(2.0)
+    assert s[4, 4, 1] == pytest.approx(2.0 * (3 / 4) ** 2)
+    assert s[4, 4, 3] == pytest.approx(2.0 * (1 / 4) ** 2)
+    prof = s[7, 7, :]
+    assert np.all(np.diff(prof[:4]) < 0) and np.all(np.diff(prof[-4:]) > 0)
+    sm = oracle.sigma_max_default(g, 3000.0)
+    assert sm == pytest.approx(3 * 3000.0 * math.log(1000.0) / (2 * 4 * 10.0))
+    assert oracle.sigma_max_default(oracle.Grid((5, 5), (1, 1), (0, 0), 2, 0), 1.0) == 0.0
+
+
+# ---------------------------------------------------------- Ricker (input)
+def test_ricker_closed_form():
+    f = 12.5
+    dt = 1e-4                                     # t0 = 1/f = 800 dt
+    w = synth.ricker(4000, dt, f)
+    t0 = 1.0 / f
+    assert w[int(round(t0 / dt))] == pytest.approx(1.0, abs=1e-12)
+    tz = t0 + 1.0 / (math.pi * f * math.sqrt(2.0))
+    k = int(tz / dt)
+    assert w[k] * w[k + 1] <= 0.0                 # zero crossing bracketed
+    assert np.argmax(w) == int(round(t0 / dt))
+
+
+# ---------------------------------------------------------- stepping (O6)
+def _plane_wave(g, k, v, dt):
+    """Discrete plane wave cos(k.x - w_d t): (4/dt^2) sin^2(w_d dt/2) =
+    v^2 sum_a h_a^-2 (-c_0 - 2 sum_j c_j cos(j k_a h_a))."""
+    c = oracle.fd_weights(g.space_order)
+    s = 0.0
+    for a in range(g.ndim):
+        ha = g.spacing[a]
+        s += (-c[0] - 2.0 * sum(c[j] * math.cos(j * k[a] * ha) for j in range(1, len(c)))) / ha ** 2
+    wd = 2.0 / dt * math.asin(math.sqrt(v * v * s * dt * dt / 4.0))
+    return wd
+
+
+@pytest.mark.parametrize("ndim,so", [(2, 4), (2, 16), (3, 8), (3, 2)])
+def test_discrete_plane_wave_exact(ndim, so):
+    nt = 3
+    base = 2 * nt * (so // 2) + 10
+    n = (base + 6, base + 2, base)[:ndim]
+    h = (10.0, 12.0, 9.0)[:ndim]
+    g = oracle.Grid(n, h, (0.0,) * ndim, so)
+    v = 2000.0
+    dt = 0.9 * oracle.critical_dt(g, v)
+    k = (0.021, -0.013, 0.017)[:ndim]
+    wd = _plane_wave(g, k, v, dt)
+    coords = np.meshgrid(*[np.arange(m) * hh for m, hh in zip(reversed(n), reversed(h))], indexing="ij")
+    phase = sum(k[a] * coords[ndim - 1 - a] for a in range(ndim))
+    u0 = np.cos(phase)
+    um = np.cos(phase + wd * dt)
+    vp = np.full(g.array_shape, v)
+    rec, u, _, _ = oracle.forward(g, vp, np.zeros(g.array_shape), dt, nt, [tuple(0.0 for _ in h)],
+                                  np.zeros((nt, 1)), [tuple(0.0 for _ in h)], u0=u0, u_prev=um)
+    exact = np.cos(phase - wd * nt * dt)
+    m = nt * g.radius
+    sl = tuple(slice(m, -m) for _ in range(ndim))
+    assert np.max(np.abs(u[sl] - exact[sl])) < 1e-11
+    # near the faces the zero extension must show (O(1) error), proving the
+    # check above is not vacuous
+    assert np.max(np.abs(u - exact)) > 1e-3
+
+
+def _smooth_bump(g, centre, width):
+    coords = np.meshgrid(*[np.arange(m) * hh for m, hh in zip(reversed(g.padded), reversed(g.spacing))],
+                         indexing="ij")
+    r2 = sum((coords[g.ndim - 1 - a] - centre[a]) ** 2 for a in range(g.ndim))
+    return np.exp(-r2 / width ** 2)
+
+
+def test_energy_conserved_without_damping():
+    g = oracle.Grid((48, 40), (10.0, 10.0), (0.0, 0.0), 8)
+    rng = np.random.default_rng(3)
+    vp = 1500.0 + 1500.0 * rng.uniform(size=g.array_shape)
+    dt = 0.8 * oracle.critical_dt(g, vp.max())
+    u0 = _smooth_bump(g, (240.0, 200.0), 40.0)
+    nt = 400
+    _, _, _, hist = oracle.forward(g, vp, np.zeros(g.array_shape), dt, nt, [(0.0, 0.0)],
+                                   np.zeros((nt, 1)), [(0.0, 0.0)], u0=u0, u_prev=u0,
+                                   keep_history=True)
+    E = [oracle.energy(g, vp, dt, hist[n + 2], hist[n + 1]) for n in range(0, nt, 20)]
+    assert E[0] > 0
+    assert np.max(np.abs(np.array(E) - E[0])) <= 1e-12 * E[0]
+
+
+def test_energy_decays_with_damping():
+    g = oracle.Grid((40, 40), (10.0, 10.0), (0.0, 0.0), 4, nbl=10)
+    vp = np.full(g.array_shape, 2000.0)
+    sig = oracle.damping(g, oracle.sigma_max_default(g, 2000.0))
+    dt = 0.8 * oracle.critical_dt(g, 2000.0)
+    u0 = _smooth_bump(g, (300.0, 300.0), 50.0)
+    nt = 300
+    _, _, _, hist = oracle.forward(g, vp, sig, dt, nt, [(0.0, 0.0)], np.zeros((nt, 1)), [(0.0, 0.0)],
+                                   u0=u0, u_prev=u0, keep_history=True)
+    E = np.array([oracle.energy(g, vp, dt, hist[n + 2], hist[n + 1]) for n in range(nt)])
+    assert np.all(np.diff(E) <= 1e-12 * E[0])
+    assert E[-1] < 0.5 * E[0]
+
+
+def test_time_order_two():
+    """With the continuous frequency w = v|k| and a fine space order, the
+    error after a fixed time falls 4x per halving of dt."""
+    g = oracle.Grid((64, 64), (10.0, 10.0), (0.0, 0.0), 16)
+    v = 2000.0
+    k = (0.012, 0.009)
+    w = v * math.hypot(*k)
+    coords = np.meshgrid(np.arange(64) * 10.0, np.arange(64) * 10.0, indexing="ij")
+    phase = k[0] * coords[1] + k[1] * coords[0]
+    errs = []
+    T = 0.01
+    for dt in (T / 4, T / 8, T / 16):
+        nt = int(round(T / dt))
+        _, u, _, _ = oracle.forward(g, np.full(g.array_shape, v), np.zeros(g.array_shape), dt, nt,
+                                    [(0.0, 0.0)], np.zeros((nt, 1)), [(0.0, 0.0)],
+                                    u0=np.cos(phase), u_prev=np.cos(phase + w * dt))
+        errs.append(abs(u[32, 32] - math.cos(phase[32, 32] - w * T)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.5 and 3.5 < r2 < 4.5, errs
+
+
+@pytest.mark.parametrize("factor,stable", [(0.99, True), (1.01, False)])
+def test_stability_limit(factor, stable):
+    g = oracle.Grid((64, 64), (10.0, 10.0), (0.0, 0.0), 8)
+    v = 3000.0
+    dt = factor * oracle.critical_dt(g, v)
+    rng = np.random.default_rng(0)
+    u0 = rng.standard_normal(g.array_shape)
+    nt = 600
+    _, u, _, _ = oracle.forward(g, np.full(g.array_shape, v), np.zeros(g.array_shape), dt, nt,
+                                [(0.0, 0.0)], np.zeros((nt, 1)), [(0.0, 0.0)], u0=u0, u_prev=u0)
+    grow = np.max(np.abs(u)) / np.max(np.abs(u0))
+    if stable:
+        assert grow < 10.0
+    else:
+        assert grow > 1e3
+
+
+# ------------------------------------------------ sources, receivers, scale
+def test_on_grid_source_is_point_injection():
+    g = oracle.Grid((20, 20), (10.0, 10.0), (0.0, 0.0), 4)
+    vp = np.full(g.array_shape, 1500.0)
+    dt = 1e-3
+    wav = np.zeros((1, 1))
+    wav[0, 0] = 2.0
+    rec, u, _, _ = oracle.forward(g, vp, np.zeros(g.array_shape), dt, 1, [(50.0, 70.0)], wav,
+                                  [(50.0, 70.0)])
+    # first step from rest: u^1 = dt^2 v^2 q, q = w / (h_x h_z) at one point
+    want = dt * dt * 1500.0 ** 2 * 2.0 / 100.0
+    assert u[7, 5] == pytest.approx(want, rel=1e-14)
+    assert np.count_nonzero(u) == 1
+    assert rec[0, 0] == pytest.approx(want, rel=1e-14)
+
+
+def test_green_function_3d():
+    """Homogeneous 3D medium: trace at distance r matches w(t - r/v)/(4 pi r)
+    to dispersion accuracy, fixing the source scale and sign."""
+    n = 61
+    h = 10.0
+    g = oracle.Grid((n, n, n), (h, h, h), (0.0, 0.0, 0.0), 8)
+    v = 2000.0
+    dt = 0.4 * h / v
+    f0 = 10.0
+    nt = 170
+    wav = synth.ricker(nt, dt, f0)[:, None]
+    src = (300.0, 300.0, 300.0)
+    rdist = 200.0
+    rec_pt = (300.0 + rdist, 300.0, 300.0)
+    rec, _, _, _ = oracle.forward(g, np.full(g.array_shape, v), np.zeros(g.array_shape), dt, nt,
+                                  [src], wav, [rec_pt])
+    t = (np.arange(nt) + 1) * dt                           # rec[n] samples u^{n+1}
+    ana = synth.ricker(nt + 400, dt, f0)
+    tt = t - rdist / v
+    exact = np.interp(tt, np.arange(nt + 400) * dt, ana, left=0.0) / (4 * math.pi * rdist)
+    # window before the first reflection off the zero boundary
+    tmax = (2 * 300.0 - rdist) / v
+    sel = t < tmax - 0.5 / f0
+    err = np.linalg.norm(rec[sel, 0] - exact[sel]) / np.linalg.norm(exact[sel])
+    assert err < 3e-2, err
+    assert np.dot(rec[sel, 0], exact[sel]) > 0
+
+
+def test_green_function_2d():
+    """2D: u = (1/2 pi) int w(tau) / sqrt((t-tau)^2 - r^2/v^2) dtau."""
+    n = 121
+    h = 10.0
+    g = oracle.Grid((n, n), (h, h), (0.0, 0.0), 8)
+    v = 2000.0
+    dt = 0.4 * h / v
+    f0 = 10.0
+    nt = 300
+    wav = synth.ricker(nt, dt, f0)[:, None]
+    rec, _, _, _ = oracle.forward(g, np.full(g.array_shape, v), np.zeros(g.array_shape), dt, nt,
+                                  [(600.0, 600.0)], wav, [(800.0, 600.0)])
+    rdist = 200.0
+    t = (np.arange(nt) + 1) * dt
+    # substitute tau = t - r/v - s^2: integrand 2 w(.) / sqrt(s^2 + 2 r / v), smooth
+    s = np.linspace(0.0, 0.6, 6001)
+    ds = s[1] - s[0]
+    exact = np.zeros(nt)
+    for i, ti in enumerate(t):
+        tau = ti - rdist / v - s * s
+        wv = (1 - 2 * (math.pi * f0 * (tau - 1 / f0)) ** 2) * np.exp(-(math.pi * f0 * (tau - 1 / f0)) ** 2)
+        wv[tau < 0] = 0.0
+        fint = 2.0 * wv / np.sqrt(s * s + 2.0 * rdist / v)
+        exact[i] = (np.sum(fint) - 0.5 * (fint[0] + fint[-1])) * ds / (2 * math.pi)
+    tmax = (2 * 600.0 - rdist) / v
+    sel = t < tmax - 0.5 / f0
+    err = np.linalg.norm(rec[sel, 0] - exact[sel]) / np.linalg.norm(exact[sel])
+    assert err < 3e-2, err
+
+
+def _hetero_setup(ndim=2):
+    if ndim == 2:
+        g = oracle.Grid((30, 26), (10.0, 8.0), (5.0, -3.0), 4, nbl=5)
+    else:
+        g = oracle.Grid((16, 14, 12), (10.0, 9.0, 8.0), (0.0, 0.0, 0.0), 6, nbl=4)
+    rng = np.random.default_rng(11)
+    v = 1500.0 + 2000.0 * rng.uniform(size=tuple(reversed(g.shape)))
+    vp = oracle.pad_velocity(g, v)
+    sig = oracle.damping(g, oracle.sigma_max_default(g, vp.max()))
+    dt = 0.5 * oracle.critical_dt(g, vp.max())
+    return g, vp, sig, dt
+
+
+def test_reciprocity():
+    g, vp, sig, dt = _hetero_setup(2)
+    nt = 150
+    wav = synth.ricker(nt, dt, 25.0)[:, None]
+    A = (5.0 + 83.3, -3.0 + 61.7)
+    B = (5.0 + 217.1, -3.0 + 140.2)
+    rab, *_ = oracle.forward(g, vp, sig, dt, nt, [A], wav, [B])
+    rba, *_ = oracle.forward(g, vp, sig, dt, nt, [B], wav, [A])
+    assert np.linalg.norm(rab) > 0
+    assert np.linalg.norm(rab - rba) <= 1e-12 * np.linalg.norm(rab)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_adjoint_dot_product(ndim):
+    g, vp, sig, dt = _hetero_setup(ndim)
+    nt = 60
+    rng = np.random.default_rng(4)
+    ext = [(n - 1) * hh for n, hh in zip(g.shape, g.spacing)]
+    src = [tuple(o + rng.uniform(0, e) for o, e in zip(g.origin, ext)) for _ in range(3)]
+    rec = [tuple(o + rng.uniform(0, e) for o, e in zip(g.origin, ext)) for _ in range(5)]
+    w = rng.standard_normal((nt, 3))
+    r = rng.standard_normal((nt, 5))
+    Fw, *_ = oracle.forward(g, vp, sig, dt, nt, src, w, rec)
+    Ftr, _ = oracle.adjoint(g, vp, sig, dt, nt, src, rec, r)
+    lhs = float(np.sum(Fw * r))
+    rhs = float(np.sum(w * Ftr))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+
+
+def test_gradient_matches_finite_differences():
+    """O12 against central differences of J in m on the padded grid, and a
+    Taylor remainder of second order."""
+    g, vp, sig, dt = _hetero_setup(2)
+    nt = 80
+    src = [(5.0 + 141.0, -3.0 + 22.0)]
+    recs = [(5.0 + 30.0 * i + 7.0, -3.0 + 180.0) for i in range(8)]
+    wav = synth.ricker(nt, dt, 25.0)[:, None]
+    v_true = vp.copy()
+    v_true[12:18, 14:20] *= 1.1
+    d_obs, *_ = oracle.forward(g, v_true, sig, dt, nt, src, wav, recs)
+    J0, grad, _ = oracle.gradient(g, vp, sig, dt, nt, src, wav, recs, d_obs)
+    m0 = 1.0 / vp ** 2
+    rng = np.random.default_rng(9)
+    dm = rng.standard_normal(g.array_shape) * m0 * 0.01
+
+    def J(m):
+        rec, *_ = oracle.forward(g, 1.0 / np.sqrt(m), sig, dt, nt, src, wav, recs)
+        return oracle.misfit(rec, d_obs)[0]
+
+    eps = 1e-2
+    fd = (J(m0 + eps * dm) - J(m0 - eps * dm)) / (2 * eps)
+    an = float(np.sum(grad * dm))
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    rem = [abs(J(m0 + e * dm) - J0 - e * an) for e in (0.1, 0.05)]
+    assert 3.5 < rem[0] / rem[1] < 4.5
+    # perturbation confined to the damping layer, where the sigma term of
+    # O12 is of the same order as the second time difference
+    dm_layer = np.where(sig > 0, dm, 0.0)
+    fd = (J(m0 + eps * dm_layer) - J(m0 - eps * dm_layer)) / (2 * eps)
+    an = float(np.sum(grad * dm_layer))
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
