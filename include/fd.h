@@ -1,0 +1,244 @@
+/*
+ * fd.h -- C ABI of libfd, an MI355X (gfx950) finite-difference stepper for
+ * the second-order acoustic wave equation with a damping layer, off-grid
+ * point sources and receivers, its exact discrete adjoint and the
+ * imaging-condition gradient, plus a continuous-batching shot server.
+ *
+ * The calls follow the way the thesis states a finite-difference problem
+ * (Section 2.1.1): a Grid with a shape and an extent, a TimeFunction with a
+ * time order and a space order (time order is 2 here), a Function for the
+ * medium, SparseTimeFunctions for sources and receivers, and an Operator
+ * applied for nt steps with a time step dt.  Sources and receivers are the
+ * per-step work that its GPU backend could not own (Section 6.2.1); here they
+ * run on the device inside the step.  Datasets are reached through opaque
+ * handles as in the structured-mesh API of Section 2.2, but -- unlike that
+ * API, which takes ownership of the data -- the caller owns every device
+ * buffer: the library sizes a workspace, borrows it, and never frees it.
+ *
+ * Equations (readings of the thesis; the stepper is the centred leapfrog):
+ *   m u_tt + m sigma u_t - Lap_h u = q,   m = 1/v^2
+ *   u^{n+1} = [2u^n - (1 - sigma dt/2) u^{n-1} + dt^2 v^2 (Lap_h u^n + q^n)]
+ *             / (1 + sigma dt/2)
+ *   Lap_h: maximal-order central 2nd-derivative weights of space order so
+ *   (radius r = so/2 per axis, star stencil of Section 3.3.3), the field
+ *   taken as zero outside the padded grid.
+ *   sigma(i) = damp_max * sum_a (d_a/nbl)^2, d_a = distance into the layer.
+ *   q^n = sum_s w_s[n] W_s / prod(h)  (multilinear weights W over the 2^d
+ *   corners of the cell holding the source); rec_r[n] = sum W_r u^{n+1}.
+ *
+ * Conventions shared by every call:
+ *   - Return FD_OK (0) or a negative fd_status; fd_last_error() gives a
+ *     thread-local message.  No C++ exception crosses the ABI.
+ *   - "device" pointers are HIP device pointers on the device current when
+ *     the grid was created; "host" pointers are ordinary host memory read
+ *     before the call returns.
+ *   - Calls taking a stream (hipStream_t passed as void*, NULL = the null
+ *     stream) enqueue their work and return without synchronising, unless
+ *     stated otherwise; device errors raised by enqueued work surface as
+ *     FD_ERR_DEVICE on a later call.  Calls on one grid must be ordered on
+ *     one stream (they share the grid's wavefield buffers).
+ *   - Dense padded fields (initial/final states, gradients) are C arrays
+ *     [Nz'][Ny'][Nx'] (3D) or [Nz'][Nx'] (2D), x fastest, N' = N + 2 nbl.
+ *   - Coordinates are metres in grid axis order: (x, y, z) or (x, z);
+ *     a coordinate outside [origin, origin + (N-1) h] gives FD_ERR_ARG.
+ */
+#ifndef FD_H
+#define FD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FD_API_VERSION 1
+
+typedef enum fd_status {
+    FD_OK = 0,
+    FD_ERR_ARG = -1,       /* invalid argument or descriptor */
+    FD_ERR_UNSTABLE = -2,  /* dt at or above the von Neumann limit */
+    FD_ERR_NOMEM = -3,     /* workspace too small / HBM budget exceeded */
+    FD_ERR_DEVICE = -4,    /* a HIP call or an enqueued kernel failed */
+    FD_ERR_STATE = -5,     /* call not valid in the object's state */
+    FD_ERR_TIMEOUT = -6    /* fd_wait timed out */
+} fd_status;
+
+typedef enum fd_storage {
+    FD_STORE_F32 = 0,      /* float32 wavefields */
+    FD_STORE_F16 = 1,      /* IEEE half wavefields (scaled by amp_scale), FP32 arithmetic */
+    FD_STORE_BF16 = 2      /* bfloat16 wavefields, FP32 arithmetic */
+} fd_storage;
+
+/* Grid description (Devito Grid + TimeFunction, Section 2.1.1). */
+typedef struct fd_grid_desc {
+    int ndim;              /* 2 or 3 */
+    int shape[3];          /* physical points per axis, (x, y, z) or (x, z); each >= 2 */
+    double spacing[3];     /* h per axis, metres, > 0 */
+    double origin[3];      /* coordinate of the first physical point */
+    int space_order;       /* even, 2..16 (stencil radius so/2) */
+    int nbl;               /* damping-layer points added on every face, >= 0 */
+    double damp_max;       /* sigma_max in 1/s; <= 0 selects 3 v_max ln(1000) / (2 nbl h_min) */
+    int storage;           /* fd_storage */
+    float amp_scale;       /* 16-bit storage keeps amp_scale * u; 0 selects 1 */
+    int vp_padded;         /* 0: vp given on the physical grid, layer filled by edge
+                              replication; 1: vp given on the padded grid */
+    int max_src;           /* capacity of the source table (points), 0 selects 64 */
+    int max_rec;           /* capacity of the receiver table (points), 0 selects 4096 */
+    int zchunk;            /* planes marched per workgroup in 3D, 0 selects automatically */
+} fd_grid_desc;
+
+/* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
+typedef struct fd_shot {
+    int nsrc;                  /* >= 1 */
+    const double *src_xyz;     /* host, [nsrc][ndim] */
+    const float *src_wavelet;  /* device, [nt][nsrc]; row n enters u^{n+1} */
+    int nrec;                  /* >= 1 */
+    const double *rec_xyz;     /* host, [nrec][ndim] */
+} fd_shot;
+
+/* Optional state for fd_forward (all device, dense padded float32, nullable). */
+typedef struct fd_fwd_opts {
+    const float *u0;       /* u^0 (NULL: zero) */
+    const float *u_prev;   /* u^{-1} (NULL: zero) */
+    float *save_u;         /* receives u^{nt} */
+    float *save_u_prev;    /* receives u^{nt-1} */
+} fd_fwd_opts;
+
+/* Read-only facts about a created grid. */
+typedef struct fd_grid_info {
+    int ndim;
+    int padded[3];         /* N' per axis (x, y, z) or (x, z) */
+    long long padded_points;
+    double vmax;           /* max velocity over the padded grid, m/s */
+    double critical_dt;    /* von Neumann limit of the undamped update */
+    double damp_max;       /* sigma_max in use, 1/s */
+    size_t field_bytes;    /* one wavefield buffer as laid out on the device */
+} fd_grid_info;
+
+typedef struct fd_grid fd_grid;
+
+/*
+ * Bytes of device workspace fd_grid_create needs for this description.
+ * Returns FD_ERR_ARG for an invalid description.
+ */
+int fd_grid_workspace_bytes(const fd_grid_desc *desc, size_t *bytes);
+
+/*
+ * Create a grid on the current device.  workspace: device buffer of at least
+ * fd_grid_workspace_bytes(desc) bytes, 256-byte aligned, borrowed until
+ * fd_grid_destroy.  vp_dev: device float32 velocity in m/s, dense, physical
+ * or padded shape per desc->vp_padded, all values > 0; read during the call.
+ * Synchronises `stream` once (to learn v_max).  *out receives the handle.
+ */
+int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t ws_bytes,
+                   const float *vp_dev, void *stream, fd_grid **out);
+
+/* Release the handle (host memory only; the workspace stays the caller's).
+ * Waits for the work last enqueued on the grid (its latest stream) first. */
+int fd_grid_destroy(fd_grid *grid);
+
+int fd_grid_get_info(const fd_grid *grid, fd_grid_info *info);
+
+/*
+ * Forward modelling: nt steps of the update from u^0, u^{-1} (zero unless
+ * opts says otherwise) with dt (FD_ERR_UNSTABLE if dt >= critical_dt).
+ * rec_out: device float32 [nt][nrec], row n = receivers sampling u^{n+1}.
+ * opts may be NULL.
+ */
+int fd_forward(fd_grid *grid, const fd_shot *shot, int nt, double dt,
+               float *rec_out, const fd_fwd_opts *opts, void *stream);
+
+/*
+ * Adjoint modelling (the exact transpose of fd_forward for a fixed medium,
+ * zero initial state): residual_dev [nt][nrec] device float32 is injected at
+ * the receivers backwards in time; src_adj_dev [nt][nsrc] device float32
+ * receives (F^T r)_s[n] = dt^2/prod(h) sum_c W_s,c lambda^n.
+ */
+int fd_adjoint(fd_grid *grid, const fd_shot *shot, int nt, double dt,
+               const float *residual_dev, float *src_adj_dev, void *stream);
+
+/* Flags for fd_gradient. */
+#define FD_GRAD_RESIDUAL_GIVEN 1   /* d_obs_dev holds the residual itself */
+
+/* Device workspace for fd_gradient: checkpoints of (u^c, u^{c-1}) every
+ * checkpoint_every steps, a recompute buffer of checkpoint_every+2 fields,
+ * and the traces and residual. */
+int fd_gradient_workspace_bytes(const fd_grid *grid, int nt, int nrec,
+                                int checkpoint_every, size_t *bytes);
+
+/*
+ * Misfit and gradient with respect to m = 1/v^2 on the padded grid:
+ *   J = 1/2 sum_n sum_r (rec_r[n] - d_obs_r[n])^2
+ *   g_m = - sum_n lambda^n [(u^{n+1} - 2u^n + u^{n-1}) + (sigma dt/2)(u^{n+1} - u^{n-1})]
+ * with lambda the adjoint field driven by the residual.  Forward wavefields
+ * are recomputed from checkpoints.  d_obs_dev: device float32 [nt][nrec]
+ * (the residual itself when flags has FD_GRAD_RESIDUAL_GIVEN).
+ * misfit_dev: device double[1]; grad_m_dev: device double, dense padded;
+ * rec_out (nullable): device float32 [nt][nrec]; src_adj (nullable): device
+ * float32 [nt][nsrc] receives F^T of the residual.
+ */
+int fd_gradient(fd_grid *grid, const fd_shot *shot, int nt, double dt,
+                const float *d_obs_dev, int checkpoint_every, int flags,
+                void *workspace, size_t ws_bytes,
+                double *misfit_dev, double *grad_m_dev, float *rec_out,
+                float *src_adj, void *stream);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop that admits shots of different grids by an HBM budget,
+ * keeps their wavefields resident, and interleaves their steps on the device
+ * (continuous batching: a request arriving while others run starts as soon
+ * as a slot and memory are free).  The server owns one device arena of
+ * hbm_budget_bytes, carved per request.
+ */
+typedef struct fd_server_desc {
+    int device;                /* HIP device ordinal */
+    size_t hbm_budget_bytes;   /* arena size; admission never exceeds it */
+    int max_slots;             /* requests resident at once, >= 1 */
+    int steps_per_round;       /* steps enqueued per request per scheduler round, 0 selects 50 */
+} fd_server_desc;
+
+typedef struct fd_request {
+    fd_grid_desc grid;         /* grid of this shot */
+    const float *vp_host;      /* host float32 velocity (copied at admission) */
+    int nsrc;
+    const double *src_xyz;     /* host [nsrc][ndim] */
+    const float *wavelet_host; /* host [nt][nsrc] (copied at submission) */
+    int nrec;
+    const double *rec_xyz;     /* host [nrec][ndim] */
+    int nt;
+    double dt;
+    float *rec_out_host;       /* host [nt][nrec], written before the ticket completes */
+} fd_request;
+
+typedef struct fd_result {
+    int status;                /* fd_status of the request */
+    double t_submit;           /* seconds on the server's clock */
+    double t_start;            /* admission time */
+    double t_done;             /* completion time */
+    size_t bytes_reserved;     /* arena bytes the request held */
+} fd_result;
+
+typedef struct fd_server fd_server;
+
+int fd_server_create(const fd_server_desc *desc, fd_server **out);
+/* Copy the request's host inputs and queue it; returns at once. */
+int fd_submit(fd_server *srv, const fd_request *req, uint64_t *ticket);
+/* Block until the ticket completes or timeout_s passes (FD_ERR_TIMEOUT);
+ * timeout_s < 0 waits forever.  A completed ticket can be waited once. */
+int fd_wait(fd_server *srv, uint64_t ticket, double timeout_s, fd_result *result);
+/* Bytes of the request's reservation (what admission charges against the budget). */
+int fd_request_bytes(const fd_request *req, size_t *bytes);
+/* Server-wide counters: peak arena bytes in use and peak resident requests. */
+int fd_server_stats(fd_server *srv, size_t *peak_bytes, int *peak_slots);
+/* Finish all queued work, then release the arena. */
+int fd_server_destroy(fd_server *srv);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD_H */

@@ -1,0 +1,167 @@
+"""ctypes mirror of include/fd.h and the loader of the in-tree libfd.so.
+
+There is no fallback: if the HIP library is not built, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfd.so")
+
+FD_OK = 0
+FD_ERR_ARG = -1
+FD_ERR_UNSTABLE = -2
+FD_ERR_NOMEM = -3
+FD_ERR_DEVICE = -4
+FD_ERR_STATE = -5
+FD_ERR_TIMEOUT = -6
+
+FD_STORE_F32 = 0
+FD_STORE_F16 = 1
+FD_STORE_BF16 = 2
+
+FD_GRAD_RESIDUAL_GIVEN = 1
+
+# every symbol include/fd.h declares
+EXPORTS = (
+    "fd_grid_workspace_bytes", "fd_grid_create", "fd_grid_destroy", "fd_grid_get_info",
+    "fd_forward", "fd_adjoint", "fd_gradient_workspace_bytes", "fd_gradient",
+    "fd_server_create", "fd_submit", "fd_wait", "fd_request_bytes", "fd_server_stats",
+    "fd_server_destroy", "fd_last_error",
+)
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("shape", ctypes.c_int * 3),
+        ("spacing", ctypes.c_double * 3),
+        ("origin", ctypes.c_double * 3),
+        ("space_order", ctypes.c_int),
+        ("nbl", ctypes.c_int),
+        ("damp_max", ctypes.c_double),
+        ("storage", ctypes.c_int),
+        ("amp_scale", ctypes.c_float),
+        ("vp_padded", ctypes.c_int),
+        ("max_src", ctypes.c_int),
+        ("max_rec", ctypes.c_int),
+        ("zchunk", ctypes.c_int),
+    ]
+
+
+class Shot(ctypes.Structure):
+    _fields_ = [
+        ("nsrc", ctypes.c_int),
+        ("src_xyz", ctypes.c_void_p),
+        ("src_wavelet", ctypes.c_void_p),
+        ("nrec", ctypes.c_int),
+        ("rec_xyz", ctypes.c_void_p),
+    ]
+
+
+class FwdOpts(ctypes.Structure):
+    _fields_ = [
+        ("u0", ctypes.c_void_p),
+        ("u_prev", ctypes.c_void_p),
+        ("save_u", ctypes.c_void_p),
+        ("save_u_prev", ctypes.c_void_p),
+    ]
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("padded", ctypes.c_int * 3),
+        ("padded_points", ctypes.c_longlong),
+        ("vmax", ctypes.c_double),
+        ("critical_dt", ctypes.c_double),
+        ("damp_max", ctypes.c_double),
+        ("field_bytes", ctypes.c_size_t),
+    ]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int),
+        ("hbm_budget_bytes", ctypes.c_size_t),
+        ("max_slots", ctypes.c_int),
+        ("steps_per_round", ctypes.c_int),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("grid", GridDesc),
+        ("vp_host", ctypes.c_void_p),
+        ("nsrc", ctypes.c_int),
+        ("src_xyz", ctypes.c_void_p),
+        ("wavelet_host", ctypes.c_void_p),
+        ("nrec", ctypes.c_int),
+        ("rec_xyz", ctypes.c_void_p),
+        ("nt", ctypes.c_int),
+        ("dt", ctypes.c_double),
+        ("rec_out_host", ctypes.c_void_p),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("bytes_reserved", ctypes.c_size_t),
+    ]
+
+
+class FDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libfd error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libfd.so (built by ``python -m paper_1906_10811_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfd.so is not built (%s); run `python -m paper_1906_10811_amd.build`"
+                           % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    PS = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "fd_grid_workspace_bytes": (I, [ctypes.POINTER(GridDesc), PS]),
+        "fd_grid_create": (I, [ctypes.POINTER(GridDesc), P, S, P, P, ctypes.POINTER(P)]),
+        "fd_grid_destroy": (I, [P]),
+        "fd_grid_get_info": (I, [P, ctypes.POINTER(GridInfo)]),
+        "fd_forward": (I, [P, ctypes.POINTER(Shot), I, D, P, ctypes.POINTER(FwdOpts), P]),
+        "fd_adjoint": (I, [P, ctypes.POINTER(Shot), I, D, P, P, P]),
+        "fd_gradient_workspace_bytes": (I, [P, I, I, I, PS]),
+        "fd_gradient": (I, [P, ctypes.POINTER(Shot), I, D, P, I, I, P, S, P, P, P, P, P]),
+        "fd_server_create": (I, [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]),
+        "fd_submit": (I, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "fd_wait": (I, [P, ctypes.c_uint64, D, ctypes.POINTER(Result)]),
+        "fd_request_bytes": (I, [ctypes.POINTER(Request), PS]),
+        "fd_server_stats": (I, [P, PS, ctypes.POINTER(ctypes.c_int)]),
+        "fd_server_destroy": (I, [P]),
+        "fd_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != FD_OK:
+        msg = load().fd_last_error().decode(errors="replace")
+        raise FDError(rc, msg)

@@ -1,0 +1,875 @@
+// fd_api.cpp -- host side of libfd: descriptors, workspace layout, sparse
+// tables, and the time loops of fd_forward / fd_adjoint / fd_gradient.
+//
+// The time loop runs on the host and enqueues one fused step kernel per time
+// step (the thesis keeps the time loop on the host and offloads the space
+// loop, Section 3.3.2 "TimeFunction"; the two time levels the update needs
+// rotate through two buffers, the n = 2 case of its t_k = (time + k) mod n
+// rotation, with the new level written over the oldest one in place).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fd.h"
+#include "fd_api_internal.h"
+#include "fd_internal.h"
+
+using namespace fd;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string t_err;
+}
+
+int fdi_fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+extern "C" const char *fd_last_error(void) { return t_err.c_str(); }
+
+#define HIPCHK(x)                                                                       \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess)                                                           \
+            return fdi_fail(FD_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e_));       \
+    } while (0)
+
+#define API_GUARD_BEGIN try {
+#define API_GUARD_END                                                                   \
+    }                                                                                   \
+    catch (const std::bad_alloc &) {                                                    \
+        return fdi_fail(FD_ERR_NOMEM, "host allocation failed");                        \
+    }                                                                                   \
+    catch (...) {                                                                       \
+        return fdi_fail(FD_ERR_STATE, "internal error");                                \
+    }
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+// Maximal-order central second-derivative weights, radius r:
+// c_j = 2 (-1)^(j+1) (r!)^2 / (j^2 (r-j)! (r+j)!), c_0 = -2 sum c_j.
+// All factorials up to 16! are exact in double.
+void second_derivative_weights(int r, double *c) {
+    auto fact = [](int n) {
+        double f = 1.0;
+        for (int i = 2; i <= n; ++i) f *= i;
+        return f;
+    };
+    double sum = 0.0;
+    for (int j = 1; j <= r; ++j) {
+        const double sgn = (j % 2 == 1) ? 1.0 : -1.0;
+        c[j] = 2.0 * sgn * fact(r) * fact(r) / ((double)j * j * fact(r - j) * fact(r + j));
+        sum += c[j];
+    }
+    c[0] = -2.0 * sum;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- grid plumbing
+bool fdi_check_desc(const fd_grid_desc *d) {
+    if (!d) return fdi_fail(FD_ERR_ARG, "null descriptor"), false;
+    if (d->ndim != 2 && d->ndim != 3) return fdi_fail(FD_ERR_ARG, "ndim must be 2 or 3"), false;
+    for (int a = 0; a < d->ndim; ++a) {
+        if (d->shape[a] < 2) return fdi_fail(FD_ERR_ARG, "shape[%d] < 2", a), false;
+        if (!(d->spacing[a] > 0.0) || !std::isfinite(d->spacing[a]))
+            return fdi_fail(FD_ERR_ARG, "spacing[%d] must be > 0", a), false;
+        if (!std::isfinite(d->origin[a])) return fdi_fail(FD_ERR_ARG, "origin[%d]", a), false;
+    }
+    if (d->space_order < 2 || d->space_order > 2 * kMaxR || d->space_order % 2)
+        return fdi_fail(FD_ERR_ARG, "space_order must be even, 2..16"), false;
+    if (d->nbl < 0) return fdi_fail(FD_ERR_ARG, "nbl < 0"), false;
+    if (d->storage < 0 || d->storage > 2) return fdi_fail(FD_ERR_ARG, "storage"), false;
+    if (d->amp_scale < 0.f || !std::isfinite(d->amp_scale)) return fdi_fail(FD_ERR_ARG, "amp_scale"), false;
+    if (d->max_src < 0 || d->max_rec < 0 || d->zchunk < 0) return fdi_fail(FD_ERR_ARG, "capacities"), false;
+    long long pts = 1;
+    for (int a = 0; a < d->ndim; ++a) pts *= (long long)d->shape[a] + 2LL * d->nbl;
+    if (pts > (1LL << 34)) return fdi_fail(FD_ERR_ARG, "grid too large"), false;
+    return true;
+}
+
+Layout fdi_layout(const fd_grid_desc *d) {
+    Layout L{};
+    const int r = d->space_order / 2;
+    L.ndim = d->ndim;
+    L.r = r;
+    L.nx = d->shape[0] + 2 * d->nbl;
+    if (d->ndim == 3) {
+        L.ny = d->shape[1] + 2 * d->nbl;
+        L.nz = d->shape[2] + 2 * d->nbl;
+        L.yh = r;
+    } else {
+        L.ny = 1;
+        L.nz = d->shape[1] + 2 * d->nbl;
+        L.yh = 0;
+    }
+    L.pitch = round_up(kXOff + round_up(L.nx, 4) + 8, 64);
+    L.nya = L.ny + 2 * L.yh;
+    L.nza = L.nz + 2 * r;
+    L.plane = (long long)L.pitch * L.nya;
+    L.elems = L.plane * L.nza;
+    return L;
+}
+
+namespace {
+
+struct SparseDev {   // device tables of one side (sources or receivers)
+    int cap = 0;     // points
+    long long *idx = nullptr;
+    float *w = nullptr;
+    int *plane_ptr = nullptr;
+    int4 *corner = nullptr;
+    int *ent_src = nullptr;
+    float *ent_w = nullptr;
+    size_t stage_off = 0;    // offset of this side's area in the host staging buffer
+};
+
+struct WsPlan {
+    size_t vel, p, uA, uB, damp, misc, total;
+    size_t src[6], rec[6];   // idx, w, plane_ptr, corner, ent_src, ent_w
+    size_t field_bytes;
+    int cap_src, cap_rec;
+    size_t stage_bytes, stage_damp, stage_src, stage_rec, stage_side_bytes_src, stage_side_bytes_rec;
+};
+
+constexpr int kNPart = 512;   // misfit partial sums
+
+size_t side_bytes(int cap, int nc, int nz, size_t off[6], size_t base) {
+    size_t o = base;
+    off[0] = o; o = align_up(o + sizeof(long long) * (size_t)cap * nc, 256);
+    off[1] = o; o = align_up(o + sizeof(float) * (size_t)cap * nc, 256);
+    off[2] = o; o = align_up(o + sizeof(int) * (size_t)(nz + 1), 256);
+    off[3] = o; o = align_up(o + sizeof(int4) * (size_t)cap * nc, 256);
+    off[4] = o; o = align_up(o + sizeof(int) * (size_t)cap * nc, 256);
+    off[5] = o; o = align_up(o + sizeof(float) * (size_t)cap * nc, 256);
+    return o - base;
+}
+
+WsPlan plan(const fd_grid_desc *d, const Layout &L) {
+    WsPlan w{};
+    const size_t esz = d->storage == FD_STORE_F32 ? 4 : 2;
+    const int nc = 1 << d->ndim;
+    w.cap_src = d->max_src ? d->max_src : 64;
+    w.cap_rec = d->max_rec ? d->max_rec : 4096;
+    w.field_bytes = align_up((size_t)L.elems * esz, 256);
+    const size_t f32 = align_up((size_t)L.elems * 4, 256);
+    size_t o = 0;
+    w.vel = o; o += f32;
+    w.p = o; o += f32;
+    w.uA = o; o += w.field_bytes;
+    w.uB = o; o += w.field_bytes;
+    w.damp = o; o = align_up(o + sizeof(float) * (size_t)(L.nx + L.ny + L.nz), 256);
+    w.misc = o; o = align_up(o + sizeof(double) * kNPart + 256, 256);
+    o += side_bytes(w.cap_src, nc, L.nz, w.src, o);
+    o += side_bytes(w.cap_rec, nc, L.nz, w.rec, o);
+    w.total = o;
+    // host staging mirrors the uploaded regions
+    size_t s = 0;
+    w.stage_damp = s; s = align_up(s + sizeof(float) * (size_t)(L.nx + L.ny + L.nz), 256);
+    w.stage_src = s;
+    w.stage_side_bytes_src = w.src[5] + align_up(sizeof(float) * (size_t)w.cap_src * nc, 256) - w.src[0];
+    s += w.stage_side_bytes_src;
+    w.stage_rec = s;
+    w.stage_side_bytes_rec = w.rec[5] + align_up(sizeof(float) * (size_t)w.cap_rec * nc, 256) - w.rec[0];
+    s += w.stage_side_bytes_rec;
+    w.stage_bytes = s;
+    return w;
+}
+
+}  // namespace
+
+struct fd_grid {
+    fd_grid_desc d;
+    int device;
+    Layout L;
+    Store st;
+    float amp;
+    int nc;
+    double c[kMaxR + 1];
+    double cell;           // prod(h)
+    char *ws;
+    size_t ws_bytes;
+    WsPlan wp;
+    float *vel, *p, *damp;
+    void *uA, *uB;
+    double *partials;
+    unsigned *vmax_bits;
+    SparseDev sd[2];       // 0 = sources, 1 = receivers
+    std::vector<double> cached_xyz[2];
+    int cached_n[2];
+    int ncorner[2];        // injection corners in the current tables
+    double vmax, dt_crit, sigma_max;
+    double dt_cached;
+    char *stage;
+    hipEvent_t stage_ev;
+    bool stage_pending;
+    int ntx, nty, ntz, zchunk;
+    hipStream_t last_stream;   // stream of the latest enqueued work
+    bool has_last_stream;
+};
+
+namespace {
+
+// ------------------------------------------------------------- staging
+int stage_acquire(fd_grid *g) {
+    if (g->stage_pending) {
+        HIPCHK(hipEventSynchronize(g->stage_ev));
+        g->stage_pending = false;
+    }
+    return FD_OK;
+}
+
+int stage_release(fd_grid *g, hipStream_t s) {
+    HIPCHK(hipEventRecord(g->stage_ev, s));
+    g->stage_pending = true;
+    return FD_OK;
+}
+
+inline void note_stream(fd_grid *g, hipStream_t s) {
+    g->last_stream = s;
+    g->has_last_stream = true;
+}
+
+// Damping tables sigma_a(i) dt / 2 = damp_max (d_a/nbl)^2 dt / 2 and p = dt^2 v^2.
+int ensure_dt(fd_grid *g, double dt, hipStream_t s) {
+    if (g->dt_cached == dt) return FD_OK;
+    const Layout &L = g->L;
+    int rc = stage_acquire(g);
+    if (rc) return rc;
+    float *tab = (float *)(g->stage + g->wp.stage_damp);
+    const int n[3] = {L.nx, L.ny, L.nz};
+    const int phys[3] = {g->d.shape[0], g->d.ndim == 3 ? g->d.shape[1] : 1,
+                         g->d.ndim == 3 ? g->d.shape[2] : g->d.shape[1]};
+    int o = 0;
+    for (int a = 0; a < 3; ++a) {
+        const bool has_layer = !(a == 1 && g->d.ndim == 2) && g->d.nbl > 0;
+        for (int i = 0; i < n[a]; ++i) {
+            double v = 0.0;
+            if (has_layer) {
+                const int nbl = g->d.nbl;
+                const int dist = std::max(0, std::max(nbl - i, i - (nbl + phys[a] - 1)));
+                const double q = (double)dist / nbl;
+                v = g->sigma_max * q * q * dt / 2.0;
+            }
+            tab[o++] = (float)v;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(g->damp, tab, sizeof(float) * o, hipMemcpyHostToDevice, s));
+    rc = stage_release(g, s);
+    if (rc) return rc;
+    HIPCHK(launch_make_p(L, g->vel, dt, g->p, s));
+    g->dt_cached = dt;
+    return FD_OK;
+}
+
+// Sparse tables of one side from host coordinates: multilinear weights of
+// the 2^d corners of the cell holding each point (cell N-2, fraction 1 for a
+// point on the last grid line), pitched offsets for sampling, and a per-plane
+// CSR of the distinct non-zero-weight corners for injection.
+int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s) {
+    const int ndim = g->d.ndim;
+    const int cap = side == 0 ? g->wp.cap_src : g->wp.cap_rec;
+    if (npts < 1) return fdi_fail(FD_ERR_ARG, "%s count must be >= 1", side ? "receiver" : "source");
+    if (npts > cap)
+        return fdi_fail(FD_ERR_ARG, "%d %s exceed the grid's capacity %d", npts,
+                        side ? "receivers" : "sources", cap);
+    if (!xyz) return fdi_fail(FD_ERR_ARG, "null coordinates");
+    std::vector<double> key(xyz, xyz + (size_t)npts * ndim);
+    if (g->cached_n[side] == npts && g->cached_xyz[side] == key) return FD_OK;
+
+    const Layout &L = g->L;
+    const int nc = g->nc;
+    std::vector<long long> idx((size_t)npts * nc);
+    std::vector<float> w((size_t)npts * nc);
+    struct Ent { int z, y, x, pt; float w; };
+    std::vector<Ent> ents;
+    ents.reserve((size_t)npts * nc);
+    for (int p = 0; p < npts; ++p) {
+        int k[3] = {0, 0, 0};
+        double fr[3] = {0, 0, 0};
+        for (int a = 0; a < ndim; ++a) {
+            const double t = (xyz[(size_t)p * ndim + a] - g->d.origin[a]) / g->d.spacing[a];
+            if (!(t >= 0.0 && t <= (double)(g->d.shape[a] - 1)))
+                return fdi_fail(FD_ERR_ARG, "%s %d outside the grid along axis %d",
+                                side ? "receiver" : "source", p, a);
+            int ki = (int)std::floor(t);
+            if (ki >= g->d.shape[a] - 1) ki = g->d.shape[a] - 2;
+            k[a] = ki;
+            fr[a] = t - ki;
+        }
+        for (int c = 0; c < nc; ++c) {
+            int ix[3] = {0, 0, 0};
+            double wt = 1.0;
+            for (int a = 0; a < ndim; ++a) {
+                const int b = (c >> a) & 1;
+                ix[a] = k[a] + b + g->d.nbl;
+                wt *= b ? fr[a] : 1.0 - fr[a];
+            }
+            int x = ix[0], y = 0, z = 0;
+            if (ndim == 3) { y = ix[1]; z = ix[2]; } else { z = ix[1]; }
+            idx[(size_t)p * nc + c] = L.offset(x, y, z);
+            w[(size_t)p * nc + c] = (float)wt;
+            if (wt != 0.0) ents.push_back({z, y, x, p, (float)wt});
+        }
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent &a, const Ent &b) {
+        if (a.z != b.z) return a.z < b.z;
+        if (a.y != b.y) return a.y < b.y;
+        if (a.x != b.x) return a.x < b.x;
+        return a.pt < b.pt;
+    });
+    std::vector<int4> corners;
+    std::vector<int> esrc;
+    std::vector<float> ew;
+    for (size_t i = 0; i < ents.size();) {
+        size_t j = i;
+        const int beg = (int)esrc.size();
+        while (j < ents.size() && ents[j].z == ents[i].z && ents[j].y == ents[i].y && ents[j].x == ents[i].x) {
+            esrc.push_back(ents[j].pt);
+            ew.push_back(ents[j].w);
+            ++j;
+        }
+        corners.push_back(make_int4(ents[i].x, ents[i].y, beg, (int)esrc.size()));
+        i = j;
+    }
+    std::vector<int> pptr(L.nz + 1, 0);
+    // plane of each corner: recover from the sorted entries
+    {
+        std::vector<int> cplane(corners.size());
+        size_t e = 0;
+        for (size_t c = 0; c < corners.size(); ++c) {
+            cplane[c] = ents[e].z;
+            e += (size_t)(corners[c].w - corners[c].z);
+        }
+        size_t c = 0;
+        for (int z = 0; z <= L.nz; ++z) {
+            while (c < corners.size() && cplane[c] < z) ++c;
+            pptr[z] = (int)c;
+        }
+    }
+
+    int rc = stage_acquire(g);
+    if (rc) return rc;
+    const size_t *off = side == 0 ? g->wp.src : g->wp.rec;
+    char *st = g->stage + (side == 0 ? g->wp.stage_src : g->wp.stage_rec);
+    const size_t base = off[0];
+    memcpy(st + (off[0] - base), idx.data(), sizeof(long long) * idx.size());
+    memcpy(st + (off[1] - base), w.data(), sizeof(float) * w.size());
+    memcpy(st + (off[2] - base), pptr.data(), sizeof(int) * pptr.size());
+    if (!corners.empty()) {
+        memcpy(st + (off[3] - base), corners.data(), sizeof(int4) * corners.size());
+        memcpy(st + (off[4] - base), esrc.data(), sizeof(int) * esrc.size());
+        memcpy(st + (off[5] - base), ew.data(), sizeof(float) * ew.size());
+    }
+    const size_t bytes = side == 0 ? g->wp.stage_side_bytes_src : g->wp.stage_side_bytes_rec;
+    HIPCHK(hipMemcpyAsync(g->ws + base, st, bytes, hipMemcpyHostToDevice, s));
+    rc = stage_release(g, s);
+    if (rc) return rc;
+    g->cached_xyz[side] = std::move(key);
+    g->cached_n[side] = npts;
+    g->ncorner[side] = (int)corners.size();
+    return FD_OK;
+}
+
+StepArgs base_args(const fd_grid *g) {
+    StepArgs a{};
+    a.L = g->L;
+    a.p = g->p;
+    a.damp = g->damp;
+    const double *h = g->d.spacing;
+    const double hx2 = h[0] * h[0];
+    const double hz2 = (g->d.ndim == 3 ? h[2] * h[2] : h[1] * h[1]);
+    const double hy2 = g->d.ndim == 3 ? h[1] * h[1] : 0.0;
+    double w0 = g->c[0] / hx2 + g->c[0] / hz2 + (g->d.ndim == 3 ? g->c[0] / hy2 : 0.0);
+    a.w0 = (float)w0;
+    for (int j = 0; j <= kMaxR; ++j) {
+        const bool in = j >= 1 && j <= g->L.r;
+        a.wx[j] = in ? (float)(g->c[j] / hx2) : 0.f;
+        a.wz[j] = in ? (float)(g->c[j] / hz2) : 0.f;
+        a.wy[j] = (in && g->d.ndim == 3) ? (float)(g->c[j] / hy2) : 0.f;
+    }
+    a.ntx = g->ntx;
+    a.nty = g->nty;
+    a.ntz = g->ntz;
+    a.zchunk = g->zchunk;
+    return a;
+}
+
+Inject make_inject(const fd_grid *g, int side, const float *vals, float scale) {
+    const SparseDev &d = g->sd[side];
+    Inject in{};
+    in.plane_ptr = d.plane_ptr;
+    in.corner = d.corner;
+    in.src = d.ent_src;
+    in.w = d.ent_w;
+    in.vals = (g->ncorner[side] > 0) ? vals : nullptr;
+    in.scale = scale;
+    return in;
+}
+
+Sample make_sample(const fd_grid *g, int side, int npts, float *out, float scale) {
+    const SparseDev &d = g->sd[side];
+    Sample s{};
+    s.npts = npts;
+    s.nc = g->nc;
+    s.idx = d.idx;
+    s.w = d.w;
+    s.out = out;
+    s.scale = scale;
+    return s;
+}
+
+inline int samp_blocks(const Sample &s) { return s.out ? (s.npts + kBlock - 1) / kBlock : 0; }
+
+int check_dt(const fd_grid *g, double dt, int nt) {
+    if (nt < 0) return fdi_fail(FD_ERR_ARG, "nt < 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fdi_fail(FD_ERR_ARG, "dt must be > 0");
+    if (dt >= g->dt_crit)
+        return fdi_fail(FD_ERR_UNSTABLE, "dt %.6g s >= stability limit %.6g s", dt, g->dt_crit);
+    return FD_OK;
+}
+
+int check_shot(const fd_grid *g, const fd_shot *sh) {
+    if (!sh) return fdi_fail(FD_ERR_ARG, "null shot");
+    if (sh->nsrc < 1 || sh->nrec < 1) return fdi_fail(FD_ERR_ARG, "nsrc and nrec must be >= 1");
+    (void)g;
+    return FD_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ public calls
+extern "C" int fd_grid_workspace_bytes(const fd_grid_desc *desc, size_t *bytes) {
+    API_GUARD_BEGIN
+    if (!bytes) return fdi_fail(FD_ERR_ARG, "null output");
+    if (!fdi_check_desc(desc)) return FD_ERR_ARG;
+    const Layout L = fdi_layout(desc);
+    *bytes = plan(desc, L).total;
+    return FD_OK;
+    API_GUARD_END
+}
+
+extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t ws_bytes,
+                              const float *vp_dev, void *stream, fd_grid **out) {
+    API_GUARD_BEGIN
+    if (!out) return fdi_fail(FD_ERR_ARG, "null output handle");
+    *out = nullptr;
+    if (!fdi_check_desc(desc)) return FD_ERR_ARG;
+    if (!workspace || !vp_dev) return fdi_fail(FD_ERR_ARG, "null workspace or velocity");
+    if ((uintptr_t)workspace % 256) return fdi_fail(FD_ERR_ARG, "workspace must be 256-byte aligned");
+    const Layout L = fdi_layout(desc);
+    const WsPlan wp = plan(desc, L);
+    if (ws_bytes < wp.total)
+        return fdi_fail(FD_ERR_NOMEM, "workspace %zu bytes < required %zu", ws_bytes, wp.total);
+    hipStream_t s = (hipStream_t)stream;
+
+    fd_grid *g = new fd_grid();
+    g->d = *desc;
+    HIPCHK(hipGetDevice(&g->device));
+    g->L = L;
+    g->st = (Store)desc->storage;
+    g->amp = (desc->storage != FD_STORE_F32 && desc->amp_scale > 0.f) ? desc->amp_scale : 1.f;
+    g->nc = 1 << desc->ndim;
+    second_derivative_weights(L.r, g->c);
+    g->cell = 1.0;
+    for (int a = 0; a < desc->ndim; ++a) g->cell *= desc->spacing[a];
+    g->ws = (char *)workspace;
+    g->ws_bytes = ws_bytes;
+    g->wp = wp;
+    g->vel = (float *)(g->ws + wp.vel);
+    g->p = (float *)(g->ws + wp.p);
+    g->uA = g->ws + wp.uA;
+    g->uB = g->ws + wp.uB;
+    g->damp = (float *)(g->ws + wp.damp);
+    g->partials = (double *)(g->ws + wp.misc);
+    g->vmax_bits = (unsigned *)(g->ws + wp.misc + sizeof(double) * kNPart);
+    for (int side = 0; side < 2; ++side) {
+        const size_t *o = side == 0 ? wp.src : wp.rec;
+        SparseDev &d = g->sd[side];
+        d.cap = side == 0 ? wp.cap_src : wp.cap_rec;
+        d.idx = (long long *)(g->ws + o[0]);
+        d.w = (float *)(g->ws + o[1]);
+        d.plane_ptr = (int *)(g->ws + o[2]);
+        d.corner = (int4 *)(g->ws + o[3]);
+        d.ent_src = (int *)(g->ws + o[4]);
+        d.ent_w = (float *)(g->ws + o[5]);
+        g->cached_n[side] = -1;
+        g->ncorner[side] = 0;
+    }
+    g->dt_cached = -1.0;
+    g->has_last_stream = false;
+    g->stage = nullptr;
+    g->stage_pending = false;
+    auto cleanup = [&](int rc) {
+        if (g->stage) (void)hipHostFree(g->stage);
+        (void)hipEventDestroy(g->stage_ev);
+        delete g;
+        return rc;
+    };
+    if (hipEventCreateWithFlags(&g->stage_ev, hipEventDisableTiming) != hipSuccess) {
+        delete g;
+        return fdi_fail(FD_ERR_DEVICE, "hipEventCreate failed");
+    }
+    if (hipHostMalloc((void **)&g->stage, wp.stage_bytes, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fdi_fail(FD_ERR_NOMEM, "pinned staging allocation failed"));
+
+    // launch geometry
+    if (desc->ndim == 3) {
+        g->ntx = (L.nx + kTileX - 1) / kTileX;
+        g->nty = (L.ny + kTileY - 1) / kTileY;
+        int zc = desc->zchunk;
+        if (zc <= 0) {
+            // about 4 resident workgroups per CU on 256 CUs, one wave of launch
+            const int tiles = g->ntx * g->nty;
+            const int nzc = std::max(1, std::min(L.nz, 1024 / std::max(1, tiles)));
+            zc = (L.nz + nzc - 1) / nzc;
+        }
+        g->zchunk = std::min(std::min(zc, L.nz), kMaxChunk);
+        g->ntz = (L.nz + g->zchunk - 1) / g->zchunk;
+    } else {
+        g->ntx = (L.nx + kTileX - 1) / kTileX;
+        g->nty = 1;
+        g->ntz = (L.nz + kTile2Z - 1) / kTile2Z;
+        g->zchunk = kTile2Z;
+    }
+
+    // zero every field (halos included), fill velocity, find v_max
+    hipError_t e = hipSuccess;
+    if ((e = launch_zero_field(L, g->uA, g->st, s)) != hipSuccess ||
+        (e = launch_zero_field(L, g->uB, g->st, s)) != hipSuccess ||
+        (e = launch_zero_field(L, g->vel, Store::F32, s)) != hipSuccess ||
+        (e = launch_zero_field(L, g->p, Store::F32, s)) != hipSuccess)
+        return cleanup(fdi_fail(FD_ERR_DEVICE, "zero fill: %s", hipGetErrorString(e)));
+    const int phys[3] = {desc->shape[0], desc->ndim == 3 ? desc->shape[1] : 1,
+                         desc->ndim == 3 ? desc->shape[2] : desc->shape[1]};
+    if ((e = launch_fill_velocity(L, vp_dev, desc->vp_padded, desc->nbl, phys, g->vel, s)) != hipSuccess ||
+        (e = hipMemsetAsync(g->vmax_bits, 0, sizeof(unsigned), s)) != hipSuccess ||
+        (e = launch_vmax(L, g->vel, g->vmax_bits, s)) != hipSuccess)
+        return cleanup(fdi_fail(FD_ERR_DEVICE, "velocity setup: %s", hipGetErrorString(e)));
+    unsigned bits = 0;
+    if ((e = hipMemcpyAsync(&bits, g->vmax_bits, sizeof bits, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return cleanup(fdi_fail(FD_ERR_DEVICE, "velocity readback: %s", hipGetErrorString(e)));
+    float vmax;
+    memcpy(&vmax, &bits, sizeof vmax);
+    if (!(vmax > 0.f) || !std::isfinite(vmax))
+        return cleanup(fdi_fail(FD_ERR_ARG, "velocity must be finite and > 0 everywhere"));
+    g->vmax = vmax;
+    // von Neumann limit: dt_crit = 1 / (v_max sqrt(sum_{j odd} c_j * sum_a h_a^-2))
+    double s_odd = 0.0;
+    for (int j = 1; j <= L.r; j += 2) s_odd += g->c[j];
+    double ih2 = 0.0;
+    for (int a = 0; a < desc->ndim; ++a) ih2 += 1.0 / (desc->spacing[a] * desc->spacing[a]);
+    g->dt_crit = 1.0 / (g->vmax * std::sqrt(s_odd * ih2));
+    double hmin = desc->spacing[0];
+    for (int a = 1; a < desc->ndim; ++a) hmin = std::min(hmin, desc->spacing[a]);
+    if (desc->nbl == 0)
+        g->sigma_max = 0.0;
+    else if (desc->damp_max > 0.0)
+        g->sigma_max = desc->damp_max;
+    else
+        g->sigma_max = 3.0 * g->vmax * std::log(1000.0) / (2.0 * desc->nbl * hmin);
+    *out = g;
+    return FD_OK;
+    API_GUARD_END
+}
+
+extern "C" int fd_grid_destroy(fd_grid *g) {
+    API_GUARD_BEGIN
+    if (!g) return FD_OK;
+    DeviceGuard dg(g->device);
+    if (g->stage_pending) (void)hipEventSynchronize(g->stage_ev);
+    if (g->has_last_stream) (void)hipStreamSynchronize(g->last_stream);
+    if (g->stage) (void)hipHostFree(g->stage);
+    (void)hipEventDestroy(g->stage_ev);
+    delete g;
+    return FD_OK;
+    API_GUARD_END
+}
+
+extern "C" int fd_grid_get_info(const fd_grid *g, fd_grid_info *info) {
+    if (!g || !info) return fdi_fail(FD_ERR_ARG, "null argument");
+    memset(info, 0, sizeof *info);
+    info->ndim = g->d.ndim;
+    info->padded[0] = g->L.nx;
+    if (g->d.ndim == 3) {
+        info->padded[1] = g->L.ny;
+        info->padded[2] = g->L.nz;
+    } else {
+        info->padded[1] = g->L.nz;
+    }
+    info->padded_points = (long long)g->L.nx * g->L.ny * g->L.nz;
+    info->vmax = g->vmax;
+    info->critical_dt = g->dt_crit;
+    info->damp_max = g->sigma_max;
+    info->field_bytes = g->wp.field_bytes;
+    return FD_OK;
+}
+
+// Enqueue forward steps n0 .. n1-1 of an nt-step run whose initial state
+// (u^0, u^{-1}) was placed in (uA, uB).  The in-place rotation puts u^n in uA
+// for even n and in uB for odd n, so a run can be advanced in chunks.
+// Receiver row n-1 is sampled inside step n; row nt-1 after the last step.
+// If ckpt is given, (u^c, u^{c-1}) is copied to ckpt[2*(c/K)], ckpt[2*(c/K)+1]
+// before step c for every multiple c of K.
+int fdi_forward_steps(fd_grid *g, const fd_shot *sh, int nt, int n0, int n1, float *rec_out,
+                      void **ckpt, int K, hipStream_t s) {
+    note_stream(g, s);
+    StepArgs a = base_args(g);
+    void *A = (n0 % 2 == 0) ? g->uA : g->uB;
+    void *B = (n0 % 2 == 0) ? g->uB : g->uA;
+    const float inj_scale = (float)(g->amp / g->cell);
+    const float smp_scale = 1.f / g->amp;
+    for (int n = n0; n < n1; ++n) {
+        if (ckpt && n % K == 0) {
+            HIPCHK(hipMemcpyAsync(ckpt[2 * (n / K)], A, g->wp.field_bytes, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(ckpt[2 * (n / K) + 1], B, g->wp.field_bytes, hipMemcpyDeviceToDevice, s));
+        }
+        a.u = A;
+        a.prev = B;
+        a.out = B;
+        a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, inj_scale);
+        a.smp = make_sample(g, 1, sh->nrec, (rec_out && n >= 1) ? rec_out + (size_t)(n - 1) * sh->nrec : nullptr,
+                            smp_scale);
+        a.nsamp_blocks = samp_blocks(a.smp);
+        HIPCHK(launch_step(a, g->st, false, s));
+        std::swap(A, B);
+    }
+    if (rec_out && n1 == nt && nt >= 1) {
+        Sample sm = make_sample(g, 1, sh->nrec, rec_out + (size_t)(nt - 1) * sh->nrec, smp_scale);
+        HIPCHK(launch_sample(sm, A, g->st, s));
+    }
+    return FD_OK;
+}
+
+// Validate a forward run and make the grid's tables current for it.
+int fdi_forward_prepare(fd_grid *g, const fd_shot *sh, int nt, double dt, hipStream_t s) {
+    int rc;
+    if (!g) return fdi_fail(FD_ERR_ARG, "null grid");
+    if ((rc = check_shot(g, sh))) return rc;
+    if ((rc = check_dt(g, dt, nt))) return rc;
+    if (nt > 0 && !sh->src_wavelet) return fdi_fail(FD_ERR_ARG, "null wavelet");
+    if ((rc = ensure_dt(g, dt, s))) return rc;
+    if ((rc = ensure_side(g, 0, sh->nsrc, sh->src_xyz, s))) return rc;
+    if ((rc = ensure_side(g, 1, sh->nrec, sh->rec_xyz, s))) return rc;
+    return FD_OK;
+}
+
+// Zero initial state (u^0 = u^{-1} = 0).
+int fdi_forward_zero_state(fd_grid *g, hipStream_t s) {
+    HIPCHK(launch_zero_field(g->L, g->uA, g->st, s));
+    HIPCHK(launch_zero_field(g->L, g->uB, g->st, s));
+    return FD_OK;
+}
+
+int fdi_grid_device(const fd_grid *g) { return g->device; }
+
+extern "C" int fd_forward(fd_grid *g, const fd_shot *sh, int nt, double dt, float *rec_out,
+                          const fd_fwd_opts *opts, void *stream) {
+    API_GUARD_BEGIN
+    if (!g) return fdi_fail(FD_ERR_ARG, "null grid");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = fdi_forward_prepare(g, sh, nt, dt, s))) return rc;
+    if (nt > 0 && !rec_out) return fdi_fail(FD_ERR_ARG, "null receiver output");
+    const Layout &L = g->L;
+    if (opts && opts->u0) HIPCHK(launch_dense_to_field(L, opts->u0, g->uA, g->st, g->amp, s));
+    else HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+    if (opts && opts->u_prev) HIPCHK(launch_dense_to_field(L, opts->u_prev, g->uB, g->st, g->amp, s));
+    else HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+    if ((rc = fdi_forward_steps(g, sh, nt, 0, nt, rec_out, nullptr, 1, s))) return rc;
+    void *cur = (nt % 2 == 0) ? g->uA : g->uB;
+    void *prv = (nt % 2 == 0) ? g->uB : g->uA;
+    if (opts && opts->save_u) HIPCHK(launch_field_to_dense(L, cur, opts->save_u, g->st, 1.f / g->amp, s));
+    if (opts && opts->save_u_prev) HIPCHK(launch_field_to_dense(L, prv, opts->save_u_prev, g->st, 1.f / g->amp, s));
+    return FD_OK;
+    API_GUARD_END
+}
+
+extern "C" int fd_adjoint(fd_grid *g, const fd_shot *sh, int nt, double dt,
+                          const float *residual, float *src_adj, void *stream) {
+    API_GUARD_BEGIN
+    if (!g) return fdi_fail(FD_ERR_ARG, "null grid");
+    int rc;
+    if ((rc = check_shot(g, sh))) return rc;
+    if ((rc = check_dt(g, dt, nt))) return rc;
+    if (nt > 0 && (!residual || !src_adj)) return fdi_fail(FD_ERR_ARG, "null residual or output");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = ensure_dt(g, dt, s))) return rc;
+    if ((rc = ensure_side(g, 0, sh->nsrc, sh->src_xyz, s))) return rc;
+    if ((rc = ensure_side(g, 1, sh->nrec, sh->rec_xyz, s))) return rc;
+    const Layout &L = g->L;
+    note_stream(g, s);
+    HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+    HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+    StepArgs a = base_args(g);
+    void *A = g->uA, *B = g->uB;   // lambda^k, lambda^{k+1}
+    const float inj_scale = (float)(g->amp / (dt * dt));
+    const float smp_scale = (float)(dt * dt / (g->cell * g->amp));
+    for (int k = nt; k >= 1; --k) {
+        a.u = A;
+        a.prev = B;
+        a.out = B;
+        a.inj = make_inject(g, 1, residual + (size_t)(k - 1) * sh->nrec, inj_scale);
+        a.smp = make_sample(g, 0, sh->nsrc, k <= nt - 1 ? src_adj + (size_t)k * sh->nsrc : nullptr, smp_scale);
+        a.nsamp_blocks = samp_blocks(a.smp);
+        HIPCHK(launch_step(a, g->st, false, s));
+        std::swap(A, B);
+    }
+    if (nt >= 1) {
+        Sample sm = make_sample(g, 0, sh->nsrc, src_adj, smp_scale);
+        HIPCHK(launch_sample(sm, A, g->st, s));
+    }
+    return FD_OK;
+    API_GUARD_END
+}
+
+namespace {
+struct GradPlan {
+    size_t ckpt, seg, rec, resid, total;
+    int ncp, K;
+};
+GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K) {
+    GradPlan p{};
+    p.K = K;
+    p.ncp = (nt + K - 1) / K;
+    const size_t fb = g->wp.field_bytes;
+    size_t o = 0;
+    p.ckpt = o; o += fb * 2 * (size_t)p.ncp;
+    p.seg = o; o += fb * (size_t)(std::min(K, nt) + 2);
+    p.rec = o; o = align_up(o + sizeof(float) * (size_t)nt * nrec, 256);
+    p.resid = o; o = align_up(o + sizeof(float) * (size_t)nt * nrec, 256);
+    p.total = o;
+    return p;
+}
+}  // namespace
+
+extern "C" int fd_gradient_workspace_bytes(const fd_grid *g, int nt, int nrec, int K, size_t *bytes) {
+    API_GUARD_BEGIN
+    if (!g || !bytes) return fdi_fail(FD_ERR_ARG, "null argument");
+    if (nt < 1 || nrec < 1 || K < 1) return fdi_fail(FD_ERR_ARG, "nt, nrec and checkpoint_every must be >= 1");
+    *bytes = grad_plan(g, nt, nrec, K).total;
+    return FD_OK;
+    API_GUARD_END
+}
+
+extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, const float *d_obs,
+                           int K, int flags, void *workspace, size_t ws_bytes, double *misfit,
+                           double *grad_m, float *rec_out, float *src_adj, void *stream) {
+    API_GUARD_BEGIN
+    if (!g) return fdi_fail(FD_ERR_ARG, "null grid");
+    int rc;
+    if ((rc = check_shot(g, sh))) return rc;
+    if ((rc = check_dt(g, dt, nt))) return rc;
+    if (nt < 1 || K < 1) return fdi_fail(FD_ERR_ARG, "nt and checkpoint_every must be >= 1");
+    if (g->st != Store::F32) return fdi_fail(FD_ERR_ARG, "fd_gradient needs float32 storage");
+    if (!d_obs || !misfit || !grad_m || !workspace || !sh->src_wavelet)
+        return fdi_fail(FD_ERR_ARG, "null pointer argument");
+    if ((uintptr_t)workspace % 256) return fdi_fail(FD_ERR_ARG, "workspace must be 256-byte aligned");
+    const GradPlan gp = grad_plan(g, nt, sh->nrec, K);
+    if (ws_bytes < gp.total) return fdi_fail(FD_ERR_NOMEM, "gradient workspace %zu < %zu", ws_bytes, gp.total);
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = ensure_dt(g, dt, s))) return rc;
+    if ((rc = ensure_side(g, 0, sh->nsrc, sh->src_xyz, s))) return rc;
+    if ((rc = ensure_side(g, 1, sh->nrec, sh->rec_xyz, s))) return rc;
+    const Layout &L = g->L;
+    char *ws = (char *)workspace;
+    const size_t fb = g->wp.field_bytes;
+    std::vector<void *> ck((size_t)2 * gp.ncp);
+    for (int i = 0; i < 2 * gp.ncp; ++i) ck[i] = ws + gp.ckpt + fb * (size_t)i;
+    const int nslot = std::min(K, nt) + 2;
+    std::vector<void *> slot(nslot);
+    for (int i = 0; i < nslot; ++i) slot[i] = ws + gp.seg + fb * (size_t)i;
+    // recompute slots are written on data points only: their halos must read zero
+    for (int i = 2; i < nslot; ++i) HIPCHK(launch_zero_field(L, slot[i], g->st, s));
+    float *recb = (float *)(ws + gp.rec);
+    float *resid = (float *)(ws + gp.resid);
+
+    // 1. forward with checkpoints of (u^c, u^{c-1}) every K steps
+    HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+    HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+    if ((rc = fdi_forward_steps(g, sh, nt, 0, nt, recb, ck.data(), K, s))) return rc;
+    // 2. residual and misfit (FP64)
+    const long long nres = (long long)nt * sh->nrec;
+    HIPCHK(launch_misfit(recb, d_obs, nres, (flags & FD_GRAD_RESIDUAL_GIVEN) ? 1 : 0, resid,
+                         g->partials, kNPart, misfit, s));
+    // 3. adjoint sweep over segments, last to first, recomputing each segment
+    HIPCHK(launch_zero_f64(grad_m, (long long)L.nx * L.ny * L.nz, s));
+    HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+    HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+    void *LA = g->uA, *LB = g->uB;   // lambda^k, lambda^{k+1}
+    StepArgs a = base_args(g);
+    const float fwd_inj = (float)(1.0 / g->cell);
+    const float adj_inj = (float)(1.0 / (dt * dt));
+    const float adj_smp = (float)(dt * dt / g->cell);
+    const int nseg = gp.ncp;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int c = seg * K;
+        const int e = std::min(c + K, nt);
+        HIPCHK(hipMemcpyAsync(slot[0], ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(slot[1], ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
+        for (int i = 0; i < e - c; ++i) {
+            a.u = slot[i + 1];
+            a.prev = slot[i];
+            a.out = slot[i + 2];
+            a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)(c + i) * sh->nsrc, fwd_inj);
+            a.smp = Sample{};
+            a.nsamp_blocks = 0;
+            a.img = Imaging{};
+            HIPCHK(launch_step(a, g->st, false, s));
+        }
+        for (int k = e; k >= c + 1; --k) {
+            a.u = LA;
+            a.prev = LB;
+            a.out = LB;
+            a.inj = make_inject(g, 1, resid + (size_t)(k - 1) * sh->nrec, adj_inj);
+            a.smp = make_sample(g, 0, sh->nsrc, (src_adj && k <= nt - 1) ? src_adj + (size_t)k * sh->nsrc : nullptr,
+                                adj_smp);
+            a.nsamp_blocks = samp_blocks(a.smp);
+            a.img.u1 = slot[k - c + 1];
+            a.img.u0 = slot[k - c];
+            a.img.um = slot[k - c - 1];
+            a.img.grad = grad_m;
+            HIPCHK(launch_step(a, g->st, true, s));
+            std::swap(LA, LB);
+        }
+    }
+    if (src_adj) {
+        Sample sm = make_sample(g, 0, sh->nsrc, src_adj, adj_smp);
+        HIPCHK(launch_sample(sm, LA, g->st, s));
+    }
+    if (rec_out)
+        HIPCHK(hipMemcpyAsync(rec_out, recb, sizeof(float) * (size_t)nres, hipMemcpyDeviceToDevice, s));
+    return FD_OK;
+    API_GUARD_END
+}

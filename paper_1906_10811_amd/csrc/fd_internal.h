@@ -1,0 +1,108 @@
+// fd_internal.h -- device layout and kernel-launch interface shared by the
+// host side of libfd (fd_api.cpp, fd_serve.cpp) and its kernels
+// (fd_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fd {
+
+constexpr int kMaxR = 8;          // space order 16
+constexpr int kXOff = 64;         // elements before x = 0 in every row (>= kMaxR, 128-B aligned)
+constexpr int kTileX = 64;        // x points per tile (16 lanes x 4 points)
+constexpr int kTileY = 16;        // y rows per 3D tile (one row per 16 lanes)
+constexpr int kTile2Z = 64;       // z rows per 2D tile
+constexpr int kBlock = 256;       // threads per workgroup
+constexpr int kMaxChunk = 256;    // z planes per 3D workgroup at most
+
+// Pitched device layout of one field: rows of `pitch` elements, x = 0 at
+// element kXOff; `yh` zero rows above and below each plane (r in 3D, 0 in
+// 2D); r zero planes before and after the grid.  Halo cells are zeroed once
+// and never written, which realises the zero extension of the Laplacian.
+struct Layout {
+    int ndim;
+    int r;
+    int nx, ny, nz;       // padded data extents; ny == 1 in 2D (axis 1 of a 2D grid is z)
+    int yh;               // y halo rows
+    int pitch;            // elements per row
+    int nya;              // rows per plane = ny + 2 yh
+    int nza;              // planes = nz + 2 r
+    long long plane;      // elements per plane = pitch * nya
+    long long elems;      // elements per field = plane * nza
+
+    __host__ __device__ long long offset(int x, int y, int z) const {
+        return ((long long)(z + r) * nya + (y + yh)) * (long long)pitch + kXOff + x;
+    }
+};
+
+// Per-plane CSR of the grid points that receive a point-source term in a
+// step.  Corner k lies at (x, y) of plane z with plane_ptr[z] <= k <
+// plane_ptr[z+1]; its value is sum_{e = beg..end-1} w[e] * vals[src[e]].
+struct Inject {
+    const int *plane_ptr;   // [nz + 1]
+    const int4 *corner;     // (x, y, beg, end)
+    const int *src;         // entry -> index into vals
+    const float *w;         // entry -> multilinear weight
+    const float *vals;      // this step's row of values, nullptr = no injection
+    float scale;            // multiplies every value
+};
+
+// Sampling of the centre field at sparse points by extra workgroups.
+struct Sample {
+    int npts;
+    int nc;                 // corners per point (2^ndim)
+    const long long *idx;   // [npts][nc] element offsets in the pitched layout
+    const float *w;         // [npts][nc]
+    float *out;             // row of npts outputs, nullptr = no sampling
+    float scale;
+};
+
+// Imaging condition fused into an adjoint step: for the new adjoint value
+// lam at a point, grad -= lam * ((u1 - 2 u0 + um) + s (u1 - um)), where s is
+// the point's sigma dt / 2.
+struct Imaging {
+    const void *u1;         // u^{n+1}
+    const void *u0;         // u^n
+    const void *um;         // u^{n-1}
+    double *grad;           // dense padded [nz][ny][nx]
+};
+
+struct StepArgs {
+    Layout L;
+    const void *u;          // centre field (read, with halo)
+    const void *prev;       // previous field (read)
+    void *out;              // new field (may alias prev: in-place update)
+    const float *p;         // dt^2 v^2, pitched FP32
+    const float *damp;      // sigma dt/2 per index: [nx] x, then [ny] y, then [nz] z
+    float w0;               // centre weight sum_a c_0 / h_a^2
+    float wx[kMaxR + 1];    // c_j / h_x^2
+    float wy[kMaxR + 1];
+    float wz[kMaxR + 1];
+    int ntx, nty, ntz;      // tiles per axis (ntz counts z chunks in 3D)
+    int zchunk;             // planes per 3D workgroup
+    int nsamp_blocks;       // leading workgroups that sample instead of stepping
+    Inject inj;
+    Sample smp;
+    Imaging img;
+};
+
+enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
+
+// Launchers (fd_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_step(const StepArgs &a, Store st, bool imaging, hipStream_t s);
+hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s);
+hipError_t launch_fill_velocity(const Layout &L, const float *vp, int vp_padded, int nbl,
+                                const int *phys, float *vel, hipStream_t s);
+hipError_t launch_vmax(const Layout &L, const float *vel, unsigned *out_bits, hipStream_t s);
+hipError_t launch_make_p(const Layout &L, const float *vel, double dt, float *p, hipStream_t s);
+hipError_t launch_zero_field(const Layout &L, void *f, Store st, hipStream_t s);
+hipError_t launch_dense_to_field(const Layout &L, const float *dense, void *f, Store st,
+                                 float scale, hipStream_t s);
+hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, Store st,
+                                 float scale, hipStream_t s);
+hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
+                         float *resid, double *partials, int npart, double *out, hipStream_t s);
+hipError_t launch_zero_f64(double *p, long long n, hipStream_t s);
+
+}  // namespace fd

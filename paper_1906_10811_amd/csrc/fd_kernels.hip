@@ -1,0 +1,691 @@
+// fd_kernels.hip -- gfx950 kernels of libfd.
+//
+// The hot loop is the per-step space loop of an explicit finite-difference
+// stepper (the thesis launches one data-parallel loop per time step from a
+// host time loop, Section 3.3.3 "Parallel loop invocation"); here one launch
+// of k_step3d / k_step2d performs the whole step:
+//
+//   lap  = w0 u + sum_j wx_j (u_{x+j} + u_{x-j}) + wy_j (..) + wz_j (..)
+//   s    = sigma dt / 2                     (per-axis tables, 0 off the layer)
+//   unew = (2u - (1 - s) uprev + p (lap + src)) / (1 + s),  p = dt^2 v^2
+//
+// with the point-source term `src` added by the thread that owns the point
+// and the receiver sampling of the centre field done by extra workgroups of
+// the same launch.  All weights are precomputed on the host (no division in
+// the inner loop: the lesson of the aggressive-DSE kernel of Section 5.1.5).
+//
+// 3D: 2.5D blocking.  A workgroup owns a 64 x 16 xy tile and marches a chunk
+// of z planes.  Each lane keeps 4 consecutive x points and a register queue
+// of the 2r+1 z values of its column; the current xy plane (tile + r halo) is
+// staged through LDS (double-buffered, one barrier per plane) for the x and y
+// neighbours.  Loads of plane z+1 are issued before plane z is computed.
+// Arithmetic is FP32 whatever the storage type.  No MFMA: the update is a
+// star stencil, not a contraction, and is bound by HBM bandwidth.
+#include "fd_internal.h"
+
+#include <stdint.h>
+
+namespace fd {
+namespace {
+
+// ------------------------------------------------------------ storage types
+template <Store S> struct Elem;
+
+template <> struct Elem<Store::F32> {
+    using T = float;
+    __device__ static float4 ld4(const T *p) { return *reinterpret_cast<const float4 *>(p); }
+    __device__ static void st4(T *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+    __device__ static float ld(const T *p) { return *p; }
+    __device__ static void st(T *p, float v) { *p = v; }
+};
+
+__device__ inline float h2f(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+__device__ inline uint16_t f2h(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+// bfloat16: upper half of the float32 pattern, round to nearest even.
+__device__ inline float b2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ inline uint16_t f2b(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <> struct Elem<Store::F16> {
+    using T = uint16_t;
+    __device__ static float4 ld4(const T *p) {
+        uint2 v = *reinterpret_cast<const uint2 *>(p);
+        return make_float4(h2f(v.x & 0xFFFF), h2f(v.x >> 16), h2f(v.y & 0xFFFF), h2f(v.y >> 16));
+    }
+    __device__ static void st4(T *p, float4 v) {
+        uint2 o;
+        o.x = (uint32_t)f2h(v.x) | ((uint32_t)f2h(v.y) << 16);
+        o.y = (uint32_t)f2h(v.z) | ((uint32_t)f2h(v.w) << 16);
+        *reinterpret_cast<uint2 *>(p) = o;
+    }
+    __device__ static float ld(const T *p) { return h2f(*p); }
+    __device__ static void st(T *p, float v) { *p = f2h(v); }
+};
+
+template <> struct Elem<Store::BF16> {
+    using T = uint16_t;
+    __device__ static float4 ld4(const T *p) {
+        uint2 v = *reinterpret_cast<const uint2 *>(p);
+        return make_float4(b2f(v.x & 0xFFFF), b2f(v.x >> 16), b2f(v.y & 0xFFFF), b2f(v.y >> 16));
+    }
+    __device__ static void st4(T *p, float4 v) {
+        uint2 o;
+        o.x = (uint32_t)f2b(v.x) | ((uint32_t)f2b(v.y) << 16);
+        o.y = (uint32_t)f2b(v.z) | ((uint32_t)f2b(v.w) << 16);
+        *reinterpret_cast<uint2 *>(p) = o;
+    }
+    __device__ static float ld(const T *p) { return b2f(*p); }
+    __device__ static void st(T *p, float v) { *p = f2b(v); }
+};
+
+__device__ inline float comp(const float4 &v, int i) {
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by hardware id.  Renumber
+// so that each XCD runs one contiguous range of logical tiles: x-neighbour
+// and y-neighbour tiles then share an L2, which serves their halo reads.
+__device__ inline int xcd_remap(int h, int G) {
+    constexpr int X = 8;
+    const int xcd = h % X, k = h / X;
+    const int per = G / X, rem = G % X;
+    return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+template <Store S>
+__device__ void sample_block(const Sample &s, const void *field, int blk) {
+    using E = Elem<S>;
+    const int i = blk * kBlock + (int)threadIdx.x;
+    if (i >= s.npts) return;
+    const typename E::T *f = (const typename E::T *)field;
+    float v = 0.f;
+    for (int c = 0; c < s.nc; ++c)
+        v += s.w[(long long)i * s.nc + c] * E::ld(f + s.idx[(long long)i * s.nc + c]);
+    s.out[i] = v * s.scale;
+}
+
+// Source term of the points (x..x+3, y) from the corners [e0, e1) of one
+// plane (all lanes of the workgroup walk the same, usually empty, list).
+__device__ inline void gather_sources(const Inject &inj, int e0, int e1, int x, int y, float &s0,
+                                      float &s1, float &s2, float &s3) {
+    for (int e = e0; e < e1; ++e) {
+        const int4 c = inj.corner[e];
+        const int d = c.x - x;
+        if (c.y == y && (unsigned)d < 4u) {
+            float v = 0.f;
+            for (int k = c.z; k < c.w; ++k) v += inj.w[k] * inj.vals[inj.src[k]];
+            v *= inj.scale;
+            s0 += d == 0 ? v : 0.f;
+            s1 += d == 1 ? v : 0.f;
+            s2 += d == 2 ? v : 0.f;
+            s3 += d == 3 ? v : 0.f;
+        }
+    }
+}
+
+__device__ inline float update_point(float c, float m, float p, float lap, float src, float s) {
+    const float alpha = (s == 0.f) ? 1.f : __builtin_amdgcn_rcpf(1.f + s);
+    const float beta = 1.f - s;
+    return alpha * (2.f * c - beta * m + p * (lap + src));
+}
+
+// ------------------------------------------------------------------ 3D step
+template <int R, Store S, bool IMG>
+__global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
+    using E = Elem<S>;
+    using T = typename E::T;
+    constexpr int HX4 = (R + 3) / 4;          // float4 halo columns per side
+    constexpr int W4 = 16 + 2 * HX4;          // float4 per LDS row
+    constexpr int LH = kTileY + 2 * R;        // LDS rows
+    __shared__ float4 lds[2][LH * W4];
+
+    const Layout L = a.L;
+    const int logical = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    if (logical < a.nsamp_blocks) {
+        sample_block<S>(a.smp, a.u, logical);
+        return;
+    }
+    int t = logical - a.nsamp_blocks;
+    const int bx = t % a.ntx;
+    t /= a.ntx;
+    const int by = t % a.nty;
+    const int bz = t / a.nty;
+    const int x0 = bx * kTileX, y0 = by * kTileY;
+    const int z0 = bz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, L.nz);
+
+    const int lane = (int)threadIdx.x;
+    // Per-plane tables of this chunk (damping along z, source CSR pointers)
+    // are staged in LDS so that the plane loop issues no uniform global load:
+    // a vector-memory wait for one would also drain the prefetched planes.
+    __shared__ float s_dz[kMaxChunk];
+    __shared__ int s_pp[kMaxChunk + 1];
+    for (int i = lane; i <= z1 - z0; i += kBlock) {
+        if (i < z1 - z0) s_dz[i] = a.damp[L.nx + L.ny + z0 + i];
+        s_pp[i] = a.inj.vals ? a.inj.plane_ptr[z0 + i] : 0;
+    }
+    const int tx = lane & 15, ty = lane >> 4;
+    const int x = x0 + 4 * tx, y = y0 + ty;
+    const bool active = (y < L.ny) && (x < L.nx);
+    // Masked lanes and halo items read a column that is zero in every row of
+    // every plane (x in [round4(nx), round4(nx)+8) is never written), so all
+    // loads are unconditional and no select waits on a load.
+    const long long zcol = L.offset((L.nx + 3) & ~3, 0, 0);
+    const long long base = active ? L.offset(x, y, 0) : zcol;
+    const long long plane = L.plane;
+
+    const T *__restrict__ U = (const T *)a.u;
+    const T *Pv = (const T *)a.prev;
+    T *O = (T *)a.out;
+    const float *__restrict__ Pp = a.p;
+
+    // Halo items of the staged plane: 2r rows above/below the tile (16 float4
+    // each) and HX4 float4 columns left/right of each tile row.
+    constexpr int NYH = 2 * R * 16;
+    constexpr int NXH = 2 * kTileY * HX4;
+    constexpr int NH = NYH + NXH;
+    constexpr int HPT = (NH + kBlock - 1) / kBlock;
+    long long hoff[HPT];
+    int hl[HPT];
+    bool hok[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+        const int i = lane + k * kBlock;
+        hl[k] = -1;
+        hok[k] = false;
+        hoff[k] = zcol;
+        if (i < NYH) {
+            const int hr = i >> 4, hc = i & 15;
+            const int ly = hr < R ? hr : kTileY + hr;
+            const int gy = y0 + ly - R, gx = x0 + 4 * hc;
+            hl[k] = ly * W4 + HX4 + hc;
+            hok[k] = (gy >= 0) && (gy < L.ny) && (gx < L.nx);
+            hoff[k] = hok[k] ? L.offset(gx, gy, 0) : zcol;
+        } else if (i < NH) {
+            const int j = i - NYH;
+            const int side = j / (kTileY * HX4);
+            const int rem = j - side * (kTileY * HX4);
+            const int row = rem / HX4, c = rem - row * HX4;
+            const int gy = y0 + row;
+            const int gx = side == 0 ? x0 - 4 * HX4 + 4 * c : x0 + kTileX + 4 * c;
+            hl[k] = (R + row) * W4 + (side == 0 ? c : HX4 + 16 + c);
+            hok[k] = (gy < L.ny) && (gx >= 0) && (gx < L.nx);
+            hoff[k] = hok[k] ? L.offset(gx, gy, 0) : zcol;
+        }
+    }
+
+    float sxy[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int xi = min(x + i, L.nx - 1);
+        sxy[i] = active ? a.damp[xi] + a.damp[L.nx + y] : 0.f;
+    }
+    float4 q[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) q[k] = E::ld4(U + base + (long long)(z0 - R + k) * plane);
+
+    float4 front = E::ld4(U + base + (long long)(z0 + R) * plane);
+    float4 hv[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) hv[k] = E::ld4(U + hoff[k] + (long long)z0 * plane);
+    float4 pv = *reinterpret_cast<const float4 *>(Pp + base + (long long)z0 * plane);
+    float4 mv = E::ld4(Pv + base + (long long)z0 * plane);
+
+    for (int z = z0; z < z1; ++z) {
+        float4 *buf = lds[(z - z0) & 1];
+        q[2 * R] = front;
+        buf[(R + ty) * W4 + HX4 + tx] = q[R];
+#pragma unroll
+        for (int k = 0; k < HPT; ++k)
+            if (hl[k] >= 0) buf[hl[k]] = hv[k];
+        const float4 pc = pv, mc = mv;
+        if (z + 1 < z1) {
+            const long long zo = (long long)(z + 1) * plane;
+            front = E::ld4(U + base + zo + (long long)R * plane);
+#pragma unroll
+            for (int k = 0; k < HPT; ++k) hv[k] = E::ld4(U + hoff[k] + zo);
+            pv = *reinterpret_cast<const float4 *>(Pp + base + zo);
+            mv = E::ld4(Pv + base + zo);
+        }
+        __syncthreads();
+
+        if (active) {
+            // x neighbours: 2*HX4+1 float4 chunks of the lane's LDS row
+            float xs[4 * (2 * HX4 + 1)];
+            const float4 *row = buf + (R + ty) * W4 + HX4 + tx;
+#pragma unroll
+            for (int c = -HX4; c <= HX4; ++c) {
+                const float4 v = (c == 0) ? q[R] : row[c];
+                xs[4 * (c + HX4) + 0] = v.x;
+                xs[4 * (c + HX4) + 1] = v.y;
+                xs[4 * (c + HX4) + 2] = v.z;
+                xs[4 * (c + HX4) + 3] = v.w;
+            }
+            float lap[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lap[i] = a.w0 * xs[4 * HX4 + i];
+#pragma unroll
+            for (int j = 1; j <= R; ++j) {
+                const float4 yp = row[j * W4], ym = row[-j * W4];
+                const float4 zp = q[R + j], zm = q[R - j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float acc = a.wx[j] * (xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j]);
+                    acc += a.wy[j] * (comp(yp, i) + comp(ym, i));
+                    acc += a.wz[j] * (comp(zp, i) + comp(zm, i));
+                    lap[i] += acc;
+                }
+            }
+            float src[4] = {0.f, 0.f, 0.f, 0.f};
+            const int e0 = s_pp[z - z0], e1 = s_pp[z - z0 + 1];
+            if (e0 < e1) gather_sources(a.inj, e0, e1, x, y, src[0], src[1], src[2], src[3]);
+            const float sz = s_dz[z - z0];
+            float un[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                un[i] = update_point(comp(q[R], i), comp(mc, i), comp(pc, i), lap[i], src[i],
+                                     sxy[i] + sz);
+            const long long off = base + (long long)z * plane;
+            const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
+            const int nvalid = L.nx - x;
+            if (nvalid >= 4) {
+                E::st4(O + off, r4);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    if (i < nvalid) E::st(O + off + i, un[i]);
+            }
+            if constexpr (IMG) {
+                const float4 f1 = E::ld4((const T *)a.img.u1 + off);
+                const float4 f0 = E::ld4((const T *)a.img.u0 + off);
+                const float4 fm = E::ld4((const T *)a.img.um + off);
+                double *g = a.img.grad + ((long long)z * L.ny + y) * L.nx + x;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (i < nvalid) {
+                        const float u1 = comp(f1, i), u0 = comp(f0, i), um = comp(fm, i);
+                        const float br = (u1 - 2.f * u0 + um) + (sxy[i] + sz) * (u1 - um);
+                        g[i] -= (double)un[i] * (double)br;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) q[k] = q[k + 1];
+    }
+}
+
+// ------------------------------------------------------------------ 2D step
+// Grid axes (x, z); tile 64 x 64 staged whole in LDS with an r halo; each
+// lane computes 4 x points in each of 4 rows.
+template <int R, Store S, bool IMG>
+__global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
+    using E = Elem<S>;
+    using T = typename E::T;
+    constexpr int HX4 = (R + 3) / 4;
+    constexpr int W4 = 16 + 2 * HX4;
+    constexpr int LH = kTile2Z + 2 * R;
+    __shared__ float4 lds[LH * W4];
+
+    const Layout L = a.L;
+    const int logical = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    if (logical < a.nsamp_blocks) {
+        sample_block<S>(a.smp, a.u, logical);
+        return;
+    }
+    const int t = logical - a.nsamp_blocks;
+    const int bx = t % a.ntx, bz = t / a.ntx;
+    const int x0 = bx * kTileX, z0 = bz * kTile2Z;
+    const int z1 = min(z0 + kTile2Z, L.nz);
+    const int lane = (int)threadIdx.x;
+    __shared__ float s_dz[kTile2Z];
+    __shared__ int s_pp[kTile2Z + 1];
+    for (int i = lane; i <= z1 - z0; i += kBlock) {
+        if (i < z1 - z0) s_dz[i] = a.damp[L.nx + L.ny + z0 + i];
+        s_pp[i] = a.inj.vals ? a.inj.plane_ptr[z0 + i] : 0;
+    }
+    const T *U = (const T *)a.u;
+    const long long zcol = L.offset((L.nx + 3) & ~3, 0, 0);   // zero in every row
+
+    for (int i = lane; i < LH * W4; i += kBlock) {
+        const int lr = i / W4, c = i - lr * W4;
+        const int gz = z0 - R + lr, gx = x0 - 4 * HX4 + 4 * c;
+        const bool ok = gz >= 0 && gz < L.nz && gx >= 0 && gx < L.nx;
+        lds[i] = E::ld4(U + (ok ? L.offset(gx, 0, gz) : zcol));
+    }
+    __syncthreads();
+
+    const int tx = lane & 15, tz = lane >> 4;
+    const int x = x0 + 4 * tx;
+    if (x >= L.nx) return;
+    const int nvalid = L.nx - x;
+    float sx[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sx[i] = a.damp[min(x + i, L.nx - 1)];
+    const T *Pv = (const T *)a.prev;
+    T *O = (T *)a.out;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int z = z0 + tz * 4 + rr;
+        if (z >= L.nz) break;
+        const float4 *row = lds + (R + tz * 4 + rr) * W4 + HX4 + tx;
+        float xs[4 * (2 * HX4 + 1)];
+#pragma unroll
+        for (int c = -HX4; c <= HX4; ++c) {
+            const float4 v = row[c];
+            xs[4 * (c + HX4) + 0] = v.x;
+            xs[4 * (c + HX4) + 1] = v.y;
+            xs[4 * (c + HX4) + 2] = v.z;
+            xs[4 * (c + HX4) + 3] = v.w;
+        }
+        float lap[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lap[i] = a.w0 * xs[4 * HX4 + i];
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const float4 zp = row[j * W4], zm = row[-j * W4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float acc = a.wx[j] * (xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j]);
+                acc += a.wz[j] * (comp(zp, i) + comp(zm, i));
+                lap[i] += acc;
+            }
+        }
+        float src[4] = {0.f, 0.f, 0.f, 0.f};
+        const int e0 = s_pp[z - z0], e1 = s_pp[z - z0 + 1];
+        if (e0 < e1) gather_sources(a.inj, e0, e1, x, 0, src[0], src[1], src[2], src[3]);
+        const long long off = L.offset(x, 0, z);
+        const float4 pc = *reinterpret_cast<const float4 *>(a.p + off);
+        const float4 mc = E::ld4(Pv + off);
+        const float4 cc = row[0];
+        const float sz = s_dz[z - z0];
+        float un[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            un[i] = update_point(comp(cc, i), comp(mc, i), comp(pc, i), lap[i], src[i], sx[i] + sz);
+        if (nvalid >= 4) {
+            E::st4(O + off, make_float4(un[0], un[1], un[2], un[3]));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (i < nvalid) E::st(O + off + i, un[i]);
+        }
+        if constexpr (IMG) {
+            const float4 f1 = E::ld4((const T *)a.img.u1 + off);
+            const float4 f0 = E::ld4((const T *)a.img.u0 + off);
+            const float4 fm = E::ld4((const T *)a.img.um + off);
+            double *g = a.img.grad + (long long)z * L.nx + x;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i < nvalid) {
+                    const float u1 = comp(f1, i), u0 = comp(f0, i), um = comp(fm, i);
+                    const float br = (u1 - 2.f * u0 + um) + (sx[i] + sz) * (u1 - um);
+                    g[i] -= (double)un[i] * (double)br;
+                }
+            }
+        }
+    }
+}
+
+template <Store S>
+__global__ void k_sample(const Sample s, const void *field) {
+    sample_block<S>(s, field, (int)blockIdx.x);
+}
+
+// --------------------------------------------------------------- utilities
+__global__ void k_fill_velocity(const Layout L, const float *vp, int vp_padded, int nbl,
+                                int px, int py, int pz, float *vel) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        float v;
+        if (vp_padded) {
+            v = vp[i];
+        } else {
+            const int ix = min(max(x - nbl, 0), px - 1);
+            const int iz = min(max(z - nbl, 0), pz - 1);
+            if (L.ndim == 3) {
+                const int iy = min(max(y - nbl, 0), py - 1);
+                v = vp[((long long)iz * py + iy) * px + ix];
+            } else {
+                v = vp[(long long)iz * px + ix];
+            }
+        }
+        vel[L.offset(x, y, z)] = v;
+    }
+}
+
+__global__ void k_vmax(const Layout L, const float *vel, unsigned *out) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    float m = 0.f;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        const float v = vel[L.offset(x, y, z)];
+        // NaN or non-positive velocities poison the maximum on purpose
+        m = (v > 0.f) ? fmaxf(m, v) : __uint_as_float(0x7F800000u);
+        if (!(v > 0.f)) break;
+    }
+    atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void k_make_p(const Layout L, const float *vel, double dt2, float *p) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        const long long o = L.offset(x, y, z);
+        const double v = (double)vel[o];
+        p[o] = (float)(dt2 * v * v);
+    }
+}
+
+template <typename T>
+__global__ void k_zero(T *f, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        f[i] = T(0);
+}
+
+template <Store S>
+__global__ void k_dense_to_field(const Layout L, const float *dense, void *f, float scale) {
+    using E = Elem<S>;
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        E::st((typename E::T *)f + L.offset(x, y, z), dense[i] * scale);
+    }
+}
+
+template <Store S>
+__global__ void k_field_to_dense(const Layout L, const void *f, float *dense, float scale) {
+    using E = Elem<S>;
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        dense[i] = E::ld((const typename E::T *)f + L.offset(x, y, z)) * scale;
+    }
+}
+
+// Misfit: residual and per-block FP64 partial sums of r^2/2 (fixed order),
+// then a single workgroup folds the partials in index order.
+__global__ void k_misfit_partial(const float *rec, const float *obs, long long n, int given,
+                                 float *resid, double *partials) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const float r = given ? obs[i] : rec[i] - obs[i];
+        if (resid) resid[i] = r;
+        acc += 0.5 * (double)r * (double)r;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void k_misfit_final(const double *partials, int npart, double *out) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < npart; i += kBlock) acc += partials[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// ------------------------------------------------------------ dispatch tables
+using StepFn = void (*)(const StepArgs);
+
+template <Store S, bool IMG, int... Rs>
+struct Table {
+    static StepFn get3(int r) {
+        StepFn f = nullptr;
+        ((r == Rs ? (f = k_step3d<Rs, S, IMG>, 0) : 0), ...);
+        return f;
+    }
+    static StepFn get2(int r) {
+        StepFn f = nullptr;
+        ((r == Rs ? (f = k_step2d<Rs, S, IMG>, 0) : 0), ...);
+        return f;
+    }
+};
+
+template <Store S, bool IMG>
+StepFn pick(int ndim, int r) {
+    using Tb = Table<S, IMG, 1, 2, 3, 4, 5, 6, 7, 8>;
+    return ndim == 3 ? Tb::get3(r) : Tb::get2(r);
+}
+
+inline int grid_for(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepArgs &a, Store st, bool imaging, hipStream_t s) {
+    StepFn f = nullptr;
+    const int r = a.L.r;
+    if (imaging) {
+        if (st != Store::F32) return hipErrorInvalidValue;   // the gradient runs in float32
+        f = pick<Store::F32, true>(a.L.ndim, r);
+    } else {
+        switch (st) {
+            case Store::F32: f = pick<Store::F32, false>(a.L.ndim, r); break;
+            case Store::F16: f = pick<Store::F16, false>(a.L.ndim, r); break;
+            case Store::BF16: f = pick<Store::BF16, false>(a.L.ndim, r); break;
+        }
+    }
+    if (!f) return hipErrorInvalidValue;
+    const int tiles = a.ntx * a.nty * a.ntz;
+    const int blocks = tiles + a.nsamp_blocks;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s) {
+    if (!smp.out || smp.npts <= 0) return hipSuccess;
+    const int blocks = (smp.npts + kBlock - 1) / kBlock;
+    switch (st) {
+        case Store::F32: hipLaunchKernelGGL(k_sample<Store::F32>, dim3(blocks), dim3(kBlock), 0, s, smp, field); break;
+        case Store::F16: hipLaunchKernelGGL(k_sample<Store::F16>, dim3(blocks), dim3(kBlock), 0, s, smp, field); break;
+        case Store::BF16: hipLaunchKernelGGL(k_sample<Store::BF16>, dim3(blocks), dim3(kBlock), 0, s, smp, field); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_velocity(const Layout &L, const float *vp, int vp_padded, int nbl,
+                                const int *phys, float *vel, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_fill_velocity, dim3(grid_for(n)), dim3(kBlock), 0, s, L, vp, vp_padded,
+                       nbl, phys[0], phys[1], phys[2], vel);
+    return hipGetLastError();
+}
+
+hipError_t launch_vmax(const Layout &L, const float *vel, unsigned *out_bits, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_vmax, dim3(grid_for(n)), dim3(kBlock), 0, s, L, vel, out_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_p(const Layout &L, const float *vel, double dt, float *p, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_make_p, dim3(grid_for(n)), dim3(kBlock), 0, s, L, vel, dt * dt, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_field(const Layout &L, void *f, Store st, hipStream_t s) {
+    if (st == Store::F32)
+        hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(L.elems)), dim3(kBlock), 0, s, (float *)f, L.elems);
+    else
+        hipLaunchKernelGGL(k_zero<uint16_t>, dim3(grid_for(L.elems)), dim3(kBlock), 0, s, (uint16_t *)f, L.elems);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double *p, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_to_field(const Layout &L, const float *dense, void *f, Store st,
+                                 float scale, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    const dim3 g(grid_for(n)), b(kBlock);
+    switch (st) {
+        case Store::F32: hipLaunchKernelGGL(k_dense_to_field<Store::F32>, g, b, 0, s, L, dense, f, scale); break;
+        case Store::F16: hipLaunchKernelGGL(k_dense_to_field<Store::F16>, g, b, 0, s, L, dense, f, scale); break;
+        case Store::BF16: hipLaunchKernelGGL(k_dense_to_field<Store::BF16>, g, b, 0, s, L, dense, f, scale); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, Store st,
+                                 float scale, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    const dim3 g(grid_for(n)), b(kBlock);
+    switch (st) {
+        case Store::F32: hipLaunchKernelGGL(k_field_to_dense<Store::F32>, g, b, 0, s, L, f, dense, scale); break;
+        case Store::F16: hipLaunchKernelGGL(k_field_to_dense<Store::F16>, g, b, 0, s, L, f, dense, scale); break;
+        case Store::BF16: hipLaunchKernelGGL(k_field_to_dense<Store::BF16>, g, b, 0, s, L, f, dense, scale); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
+                         float *resid, double *partials, int npart, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_misfit_partial, dim3(npart), dim3(kBlock), 0, s, rec, obs, n,
+                       residual_given, resid, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_misfit_final, dim3(1), dim3(kBlock), 0, s, partials, npart, out);
+    return hipGetLastError();
+}
+
+}  // namespace fd

@@ -1,0 +1,87 @@
+"""The C-ABI library loads, exports every symbol include/fd.h declares, and
+its host-only calls validate descriptors (no GPU needed, no compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1906_10811_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fd_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libfd.so is not built: run `python -m paper_1906_10811_amd.build`")
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert len(declared) >= 15
+    assert set(declared) == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _desc(**kw):
+    d = _lib.GridDesc()
+    d.ndim = kw.get("ndim", 3)
+    shp = kw.get("shape", (64, 48, 32))
+    for a in range(min(d.ndim, 3)):
+        d.shape[a] = shp[a]
+        d.spacing[a] = 10.0
+    d.space_order = kw.get("so", 8)
+    d.nbl = kw.get("nbl", 10)
+    d.storage = kw.get("storage", 0)
+    return d
+
+
+def _bytes(lib, d):
+    n = ctypes.c_size_t()
+    rc = lib.fd_grid_workspace_bytes(ctypes.byref(d), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_bytes_grow_with_grid(lib):
+    rc1, b1 = _bytes(lib, _desc(shape=(64, 48, 32)))
+    rc2, b2 = _bytes(lib, _desc(shape=(128, 48, 32)))
+    assert rc1 == 0 and rc2 == 0 and b2 > b1 > 0
+    # 4 fields (velocity, p, two wavefields) of padded points at least
+    assert b1 >= 4 * 4 * (84 * 68 * 52)
+    rc3, b3 = _bytes(lib, _desc(shape=(64, 48, 32), storage=_lib.FD_STORE_BF16))
+    assert rc3 == 0 and b3 < b1
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=4), dict(so=3), dict(so=18), dict(so=0), dict(nbl=-1), dict(shape=(1, 8, 8)),
+    dict(storage=7),
+])
+def test_invalid_descriptors_rejected(lib, bad):
+    rc, _ = _bytes(lib, _desc(**bad))
+    assert rc == _lib.FD_ERR_ARG
+    assert lib.fd_last_error().decode()
+
+
+def test_null_arguments(lib):
+    assert lib.fd_grid_workspace_bytes(None, None) == _lib.FD_ERR_ARG
+    assert lib.fd_grid_destroy(None) == 0
+    assert lib.fd_wait(None, 1, 0.0, None) == _lib.FD_ERR_ARG
+
+
+def test_request_bytes(lib):
+    r = _lib.Request()
+    r.grid = _desc(shape=(32, 32, 32), nbl=8)
+    r.nsrc, r.nrec, r.nt = 1, 16, 100
+    n = ctypes.c_size_t()
+    assert lib.fd_request_bytes(ctypes.byref(r), ctypes.byref(n)) == 0
+    _, gb = _bytes(lib, _desc(shape=(32, 32, 32), nbl=8))
+    assert n.value >= gb + 4 * 32 ** 3 + 4 * 100 * 17

@@ -1,0 +1,185 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Gate (float32 arithmetic): relative L2 error <= 1e-5 over all receivers x
+samples and over the final wavefield.  Cases span several x/y tiles and
+z chunks with ragged tails, every space order 2..16, damping layers,
+off-grid sources and receivers, and 2D and 3D grids.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import case, gpu_forward, gpu_grid, need_gpu, oracle_forward, rel_l2, torch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _print(name, **kv):
+    print(name, " ".join("%s=%.3e" % (k, v) if isinstance(v, float) else "%s=%s" % (k, v)
+                         for k, v in kv.items()), flush=True)
+
+
+def test_acoustic2d_101_workload():
+    """2D 101x101, so 4, v 1.5 km/s, 200 steps, Courant 0.4, on-grid source
+    and receivers: traces and final field vs the FP64 oracle."""
+    need_gpu()
+    w = synth.workload("acoustic2d_101")
+    c = dict(shape=w["shape"], spacing=w["spacing"], origin=w["origin"], so=w["space_order"],
+             nbl=w["nbl"], nt=w["nt"], v=synth.velocity(w), src=w["src"], rec=w["rec"], dt=w["dt"],
+             wav=synth.wavelets(w))
+    c["og"] = oracle.Grid(c["shape"], c["spacing"], c["origin"], c["so"], c["nbl"])
+    want, u_nt, _, _ = oracle_forward(c)
+    g, (rec, state) = gpu_forward(c, save_state=True)
+    e_rec = rel_l2(rec.cpu().numpy(), want)
+    e_u = rel_l2(state[0].cpu().numpy(), u_nt)
+    _print("acoustic2d_101", rec=e_rec, field=e_u)
+    assert e_rec <= TOL and e_u <= TOL
+
+
+@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16])
+@pytest.mark.parametrize("zchunk", [0, 7])
+def test_3d_every_space_order(so, zchunk):
+    """70x37x29 + 5-point layer: 2 x tiles (ragged), 3 y tiles (ragged),
+    z chunks of 7 or automatic; 3 sources, 9 receivers, 60 steps."""
+    need_gpu()
+    c = case((70, 37, 29), so, 5, 60, seed=so, nsrc=3, nrec=9)
+    want, u_nt, _, _ = oracle_forward(c)
+    g = gpu_grid(c, zchunk=zchunk)
+    _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
+    e_rec = rel_l2(rec.cpu().numpy(), want)
+    e_u = rel_l2(state[0].cpu().numpy(), u_nt)
+    _print("3d so=%d zchunk=%d" % (so, zchunk), rec=e_rec, field=e_u)
+    assert e_rec <= TOL and e_u <= TOL
+
+
+@pytest.mark.parametrize("so", [4, 16])
+def test_2d_ragged(so):
+    need_gpu()
+    c = case((67, 133), so, 6, 150, seed=3, nsrc=2, nrec=11)
+    want, u_nt, _, _ = oracle_forward(c)
+    _, (rec, state) = gpu_forward(c, save_state=True)
+    e_rec = rel_l2(rec.cpu().numpy(), want)
+    e_u = rel_l2(state[0].cpu().numpy(), u_nt)
+    _print("2d so=%d" % so, rec=e_rec, field=e_u)
+    assert e_rec <= TOL and e_u <= TOL
+
+
+def test_nx_not_multiple_of_four_and_shared_corners():
+    """nx' = 67 (partial 4-point groups); two sources in the same cell and a
+    receiver on the last grid line (cell N-2, fraction 1)."""
+    need_gpu()
+    c = case((61, 19, 23), 8, 3, 50, seed=7, nsrc=1, nrec=5)
+    s0 = c["src"][0]
+    c["src"] = [s0, (s0[0] + 1.0, s0[1] + 0.5, s0[2] - 0.7)]
+    c["wav"] = np.concatenate([c["wav"], 0.5 * c["wav"]], axis=1)
+    ext = [(n - 1) * hh for n, hh in zip(c["shape"], c["spacing"])]
+    c["rec"][0] = [o + e for o, e in zip(c["origin"], ext)]
+    want, u_nt, _, _ = oracle_forward(c)
+    _, (rec, state) = gpu_forward(c, save_state=True)
+    e_rec = rel_l2(rec.cpu().numpy(), want)
+    e_u = rel_l2(state[0].cpu().numpy(), u_nt)
+    _print("ragged nx", rec=e_rec, field=e_u)
+    assert e_rec <= TOL and e_u <= TOL
+
+
+def test_initial_state_and_resume_bitwise():
+    """Running 40 + 30 steps with the saved state equals 70 steps bitwise,
+    and an initial state given by the caller matches the oracle."""
+    need_gpu()
+    c = case((40, 33, 26), 8, 4, 70, seed=11, nsrc=1, nrec=6)
+    dev = torch.device("cuda:0")
+    g = gpu_grid(c)
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    full = g.forward(c["src"], wav, c["rec"], c["dt"])
+    r1, st = g.forward(c["src"], wav[:40].contiguous(), c["rec"], c["dt"], save_state=True)
+    r2 = g.forward(c["src"], wav[40:].contiguous(), c["rec"], c["dt"], u0=st[0], u_prev=st[1])
+    torch.cuda.synchronize()
+    both = torch.cat([r1, r2]).cpu().numpy()
+    assert np.array_equal(both, full.cpu().numpy())
+    rng = np.random.default_rng(2)
+    u0 = rng.standard_normal(c["og"].array_shape) * 1e-3
+    um = u0 * 0.99
+    c["nt"] = 25
+    c["wav"] = c["wav"][:25].copy()
+    want, u_nt, _, _ = oracle_forward(c, u0=u0, u_prev=um)
+    rec, state = g.forward(c["src"], torch.from_numpy(c["wav"]).to(dev), c["rec"], c["dt"],
+                           u0=torch.from_numpy(u0).float().to(dev), u_prev=torch.from_numpy(um).float().to(dev),
+                           save_state=True)
+    torch.cuda.synchronize()
+    assert rel_l2(rec.cpu().numpy(), want) <= TOL
+    assert rel_l2(state[0].cpu().numpy(), u_nt) <= TOL
+
+
+def test_adjoint_parity_and_dot_product():
+    need_gpu()
+    c = case((48, 37, 30), 8, 5, 70, seed=5, nsrc=2, nrec=8)
+    g = gpu_grid(c)
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal((c["nt"], 2)).astype(np.float32)
+    r = rng.standard_normal((c["nt"], 8)).astype(np.float32)
+    og = c["og"]
+    vp = oracle.pad_velocity(og, c["v"])
+    sig = oracle.damping(og, oracle.sigma_max_default(og, float(vp.max())))
+    want, _ = oracle.adjoint(og, vp, sig, c["dt"], c["nt"], c["src"], c["rec"], r.astype(np.float64))
+    got = g.adjoint(c["src"], c["rec"], torch.from_numpy(r).to(dev), c["dt"])
+    Fw = g.forward(c["src"], torch.from_numpy(w).to(dev), c["rec"], c["dt"])
+    torch.cuda.synchronize()
+    e = rel_l2(got.cpu().numpy(), want)
+    lhs = float(np.sum(Fw.cpu().numpy().astype(np.float64) * r))
+    rhs = float(np.sum(w.astype(np.float64) * got.cpu().numpy()))
+    dot = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    _print("adjoint", rel=e, dot=dot)
+    assert e <= TOL
+    assert dot <= 1e-6
+
+
+@pytest.mark.parametrize("K", [7, 200])
+def test_gradient_parity(K):
+    """fd_gradient vs the oracle's O12 gradient (checkpoint interval 7 gives
+    ragged segments; 200 > nt keeps every field)."""
+    need_gpu()
+    c = case((34, 29, 25), 8, 4, 60, seed=8, nsrc=1, nrec=6)
+    og = c["og"]
+    vp = oracle.pad_velocity(og, c["v"])
+    sig = oracle.damping(og, oracle.sigma_max_default(og, float(vp.max())))
+    v_true = vp.copy()
+    v_true[10:20, 10:20, 10:20] *= 1.05
+    d_obs, *_ = oracle.forward(og, v_true, sig, c["dt"], c["nt"], c["src"], c["wav"].astype(np.float64), c["rec"])
+    d_obs = d_obs.astype(np.float32)
+    J, grad, _ = oracle.gradient(og, vp, sig, c["dt"], c["nt"], c["src"], c["wav"].astype(np.float64),
+                                 c["rec"], d_obs.astype(np.float64))
+    g = gpu_grid(c)
+    dev = torch.device("cuda:0")
+    mis, gm, rec, _ = g.gradient(c["src"], torch.from_numpy(c["wav"]).to(dev), c["rec"],
+                                 torch.from_numpy(d_obs).to(dev), c["dt"], checkpoint_every=K)
+    torch.cuda.synchronize()
+    eJ = abs(float(mis.item()) - J) / J
+    eg = rel_l2(gm.cpu().numpy(), grad)
+    _print("gradient K=%d" % K, J=eJ, grad=eg)
+    assert eJ <= 1e-4
+    assert eg <= 1e-4
+
+
+def test_errors_are_reported():
+    need_gpu()
+    from paper_1906_10811_amd import FDError, _lib
+    c = case((20, 18, 16), 4, 2, 10, seed=1)
+    g = gpu_grid(c, max_rec=8)
+    dev = torch.device("cuda:0")
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    with pytest.raises(FDError) as e:
+        g.forward(c["src"], wav, c["rec"], 1.001 * g.critical_dt)
+    assert e.value.code == _lib.FD_ERR_UNSTABLE
+    with pytest.raises(FDError) as e:
+        g.forward([(-1.0, 0.0, 0.0)], wav, c["rec"], c["dt"])
+    assert e.value.code == _lib.FD_ERR_ARG
+    with pytest.raises(FDError) as e:
+        g.forward(c["src"], wav, np.zeros((9, 3)) + 10.0, c["dt"])
+    assert e.value.code == _lib.FD_ERR_ARG
+    # the grid still works after rejected calls
+    _, rec = gpu_forward(c, grid=g)
+    want, *_ = oracle_forward(c)
+    assert rel_l2(rec.cpu().numpy(), want) <= TOL
