@@ -1,0 +1,323 @@
+"""Benchmark of libfd on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extras all|none|...]
+
+One bench step is one fd_forward call over the whole hot path of the
+layered3d_256 workload: 256^3 physical points + 40 damping points per face
+(336^3 padded), space order 8, float32, 1000 time steps, a 15 Hz Ricker
+source half a cell off-grid and 256 receivers -- each time step one fused
+launch (stencil update, damping, source injection, receiver sampling).
+
+Throughput: Gpts/s = padded points x time steps / wall time of the step loop
+(HIP events on the stream the kernels run on, inputs resident in HBM).  The
+roofline object prices the step kernel at 16 algorithmic bytes per point
+(read u^n, u^{n-1}, dt^2 v^2; write u^{n+1}) against the 8 TB/s HBM peak.
+Extras (same JSON line): interior-only Gpts/s, the checkpointed gradient on
+gradient3d_200, 16-bit wavefield storage, and the shot server.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+B_STEP = 16.0          # algorithmic bytes per point and step, float32 wavefields
+KERNEL_SRC = os.path.join(ROOT, "paper_1906_10811_amd", "csrc", "fd_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step3d_so8_layered336.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_workload(name, torch, dev, **over):
+    w = synth.workload(name, **over)
+    v = synth.velocity(w)
+    wav = synth.wavelets(w)
+    return w, torch.from_numpy(v).to(dev), torch.from_numpy(wav).to(dev)
+
+
+def time_forward(torch, g, w, wav, steps, warmup, stream):
+    rec = torch.empty((w["nt"], len(w["rec"])), dtype=torch.float32, device=wav.device)
+    for _ in range(warmup):
+        g.forward(w["src"], wav, w["rec"], w["dt"], out=rec, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(steps):
+            g.forward(w["src"], wav, w["rec"], w["dt"], out=rec, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1000.0, rec
+
+
+def bench_headline(torch, dev, steps, warmup, stream):
+    from paper_1906_10811_amd import Grid
+    w, v, wav = make_workload("layered3d_256", torch, dev)
+    g = Grid(w["shape"], w["spacing"], v, space_order=w["space_order"], nbl=w["nbl"], origin=w["origin"],
+             stream=stream)
+    secs, rec = time_forward(torch, g, w, wav, steps, warmup, stream)
+    pts = g.padded_points
+    nt = w["nt"]
+    gpts = pts * nt * steps / secs / 1e9
+    interior = math.prod(w["shape"]) * nt * steps / secs / 1e9
+    launch_s = secs / (steps * nt)
+    achieved = B_STEP * pts / launch_s / 1e9
+    traffic = stored_traffic()
+    out = dict(gpts=gpts, interior=interior, ms_per_step=secs / steps * 1000.0, launch_us=launch_s * 1e6,
+               achieved=achieved, traffic=traffic, pts=pts, rec_norm=float(rec.norm().item()))
+    g.close()
+    return w, out
+
+
+def copy_probe(torch, dev, stream, nbytes=1 << 30, reps=5):
+    """Measured stream-copy ceiling: torch copy of a 1 GiB float32 buffer
+    (reads and writes nbytes each; reported in GB/s of read + write)."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1000.0 / reps
+    del a, b
+    return 2.0 * nbytes / secs / 1e9
+
+
+def bench_cpu_baseline(w):
+    """The FP64 oracle as it stands, on the host cores, over a bounded
+    sample: the same grid and medium, the first `nt` time steps."""
+    import oracle
+    og = oracle.Grid(tuple(w["shape"]), tuple(w["spacing"]), tuple(w["origin"]), w["space_order"], w["nbl"])
+    v = synth.velocity(w)
+    vp = oracle.pad_velocity(og, v)
+    sig = oracle.damping(og, oracle.sigma_max_default(og, float(vp.max())))
+    wav = synth.wavelets(w).astype(np.float64)
+    nt = 2
+    t0 = time.perf_counter()
+    oracle.forward(og, vp, sig, w["dt"], nt, w["src"], wav[:nt], w["rec"])
+    t1 = time.perf_counter()
+    # scale to about 15 s of work
+    nt2 = max(2, min(40, int(15.0 / max(1e-3, (t1 - t0) / nt))))
+    t0 = time.perf_counter()
+    oracle.forward(og, vp, sig, w["dt"], nt2, w["src"], wav[:nt2], w["rec"])
+    t1 = time.perf_counter()
+    pts = math.prod(og.padded)
+    return dict(value=pts * nt2 / (t1 - t0) / 1e9, unit="Gpts/s", cores=oracle.num_threads(), kind="oracle",
+                sample="layered3d_256 grid (336^3 padded, so 8, FP64), first %d of 1000 time steps, %.1f s"
+                % (nt2, t1 - t0))
+
+
+def bench_gradient(torch, dev, stream):
+    """fd_gradient on gradient3d_200: forward with checkpoints every 50 steps,
+    residual and FP64 misfit, segment recompute, adjoint with fused imaging."""
+    from paper_1906_10811_amd import Grid
+    w = synth.workload("gradient3d_200")
+    v_true = synth.velocity(w)
+    v0 = synth.smooth_model(v_true, w["spacing"], 100.0)
+    wav = torch.from_numpy(synth.wavelets(w)).to(dev)
+    gt = Grid(w["shape"], w["spacing"], torch.from_numpy(v_true).to(dev), space_order=8, nbl=w["nbl"], stream=stream)
+    d_obs = gt.forward(w["src"], wav, w["rec"], w["dt"], stream=stream)
+    torch.cuda.synchronize()
+    gt.close()
+    g = Grid(w["shape"], w["spacing"], torch.from_numpy(v0).to(dev), space_order=8, nbl=w["nbl"], stream=stream)
+    g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], checkpoint_every=w["checkpoint_every"], stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 2
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            mis, gm, _, _ = g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"],
+                                       checkpoint_every=w["checkpoint_every"], stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1000.0 / reps
+    out = dict(workload="gradient3d_200", gpts=g.padded_points * w["nt"] / secs / 1e9,
+               ms=secs * 1000.0, misfit=float(mis.item()), checkpoint_every=w["checkpoint_every"],
+               b_alg_per_pt=80)
+    g.close()
+    return out
+
+
+def bench_precision(torch, dev, stream, ref_rec):
+    """16-bit wavefield storage on layered3d_256: throughput and trace error
+    against the float32 run of the same workload."""
+    from paper_1906_10811_amd import Grid
+    w, v, wav = make_workload("layered3d_256", torch, dev)
+    res = {}
+    ref = ref_rec.double()
+    for st, scale in (("bf16", 0.0), ("f16", 1e3)):
+        g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, amp_scale=scale,
+                 stream=stream)
+        secs, rec = time_forward(torch, g, w, wav, 1, 1, stream)
+        err = float((rec.double() - ref).norm() / ref.norm())
+        res[st] = dict(gpts=g.padded_points * w["nt"] / secs / 1e9, rel_l2_vs_f32=err,
+                       b_alg_per_pt=10, amp_scale=scale)
+        g.close()
+    return res
+
+
+def bench_serving(torch, n=24, budget_gib=8.0, slots=6):
+    """Shot server: n requests with Poisson arrivals at 0.8x the measured
+    one-at-a-time capacity; reports shots/s, p50/p99 latency and the
+    throughput in Gpts/s, against plain one-at-a-time FP32 stepping."""
+    from paper_1906_10811_amd import Server
+    reqs = synth.serving_requests(n=n, seed=2, rate_hz=1.0)
+    shots = []
+    for r in reqs:
+        v = synth.layered_model(r["shape"], r["spacing"], seed=r["seed"])
+        wav = synth.ricker(r["nt"], r["dt"], r["f0"]).astype(np.float32)[:, None]
+        shots.append(dict(shape=r["shape"], spacing=r["spacing"], space_order=r["space_order"], nbl=r["nbl"],
+                          vp=v, src_xyz=r["src"], wavelet=wav, rec_xyz=r["rec"], dt=r["dt"]))
+    pts = [math.prod(s + 2 * 40 for s in r["shape"]) * r["nt"] for r in reqs]
+    srv = Server(int(budget_gib * 2 ** 30), max_slots=1)
+    t0 = time.perf_counter()
+    for s in shots:
+        srv.wait(srv.submit(**s))
+    serial = time.perf_counter() - t0
+    srv.close()
+    cap = n / serial
+    rate = 0.8 * cap
+    rng = np.random.default_rng(7)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    srv = Server(int(budget_gib * 2 ** 30), max_slots=slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for a, s in zip(arrivals, shots):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        tickets.append((time.perf_counter() - t0, srv.submit(**s)))
+    lat = []
+    for ts, t in tickets:
+        _, info = srv.wait(t)
+        lat.append(info["t_done"] - info["t_submit"])
+    total = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return dict(requests=n, budget_gib=budget_gib, slots=slots, arrival_rate_hz=rate,
+                serial_shots_per_s=cap, serial_gpts=sum(pts) / serial / 1e9,
+                shots_per_s=n / total, gpts=sum(pts) / total / 1e9,
+                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                peak_bytes=st["peak_bytes"], peak_slots=st["peak_slots"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extras", default="all", help="comma list of gradient,precision,serving or all/none")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every box in this setup has a single MI355X, and the "
+              "multi-GPU sharding of the stepper is a design, not an implementation (see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    extras = set(args.extras.split(",")) if args.extras not in ("all", "none") else (
+        {"gradient", "precision", "serving"} if args.extras == "all" else set())
+
+    copy_gbs = copy_probe(torch, dev, stream)
+    log("stream copy: %.0f GB/s" % copy_gbs)
+    log("headline: layered3d_256 forward, steps=%d warmup=%d" % (args.steps, args.warmup))
+    w, h = bench_headline(torch, dev, args.steps, args.warmup, stream)
+    log("headline: %.1f Gpts/s, %.1f us per launch" % (h["gpts"], h["launch_us"]))
+    line = {
+        "metric": "Gpts/s (3D so-8 acoustic step) & % HBM roofline; shots/s + p99 latency",
+        "value": round(h["gpts"], 3),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "layered3d_256", "grid": "256^3 + 2x40 damping (336^3 padded)",
+                   "space_order": 8, "time_steps_per_bench_step": w["nt"], "sources": 1, "receivers": 256},
+        "interior_gpts": round(h["interior"], 3),
+        "pct_hbm_roofline": round(100.0 * h["achieved"] / HBM_PEAK_GBS, 2),
+        "stream_copy_gbs": round(copy_gbs, 1),
+        "pct_of_stream_copy": round(100.0 * h["achieved"] / copy_gbs, 2),
+        "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(h["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": h["traffic"], "kernel": "k_step3d<R=4,f32>",
+                     "bytes_per_point": B_STEP, "points_per_launch": h["pts"],
+                     "avg_launch_us": round(h["launch_us"], 2)},
+    }
+    if "precision" in extras:
+        log("precision: 16-bit storage")
+        from paper_1906_10811_amd import Grid  # noqa: F401
+        w2, v2, wav2 = make_workload("layered3d_256", torch, dev)
+        g = Grid(w2["shape"], w2["spacing"], v2, space_order=8, nbl=w2["nbl"], stream=stream)
+        _, ref = time_forward(torch, g, w2, wav2, 1, 0, stream)
+        g.close()
+        line["precision"] = bench_precision(torch, dev, stream, ref)
+    if "gradient" in extras:
+        log("gradient: gradient3d_200")
+        line["gradient"] = bench_gradient(torch, dev, stream)
+    if "serving" in extras:
+        log("serving")
+        line["serving"] = bench_serving(torch)
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = bench_cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -546,9 +546,16 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
         g->nty = (L.ny + kTileY - 1) / kTileY;
         int zc = desc->zchunk;
         if (zc <= 0) {
-            // about 4 resident workgroups per CU on 256 CUs, one wave of launch
+            // One round of workgroups: as many z chunks per xy tile as the
+            // device holds resident step workgroups (occupancy x CUs), so no
+            // second, partly filled round of chunks trails the first.
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
+                cus <= 0)
+                cus = 256;
+            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, false));
             const int tiles = g->ntx * g->nty;
-            const int nzc = std::max(1, std::min(L.nz, 1024 / std::max(1, tiles)));
+            const int nzc = std::max(1, std::min(L.nz, occ * cus / std::max(1, tiles)));
             zc = (L.nz + nzc - 1) / nzc;
         }
         g->zchunk = std::min(std::min(zc, L.nz), kMaxChunk);

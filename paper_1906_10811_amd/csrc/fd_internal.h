@@ -89,6 +89,9 @@ struct StepArgs {
 
 enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
 
+// Resident workgroups per CU of a step kernel (0 if unknown).
+int step_blocks_per_cu(int ndim, int r, Store st, bool imaging);
+
 // Launchers (fd_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_step(const StepArgs &a, Store st, bool imaging, hipStream_t s);
 hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s);

@@ -227,29 +227,32 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) q[k] = E::ld4(U + base + (long long)(z0 - R + k) * plane);
 
-    float4 front = E::ld4(U + base + (long long)(z0 + R) * plane);
-    float4 hv[HPT];
+    // Loads of one plane: the queue front u(z+R), the staged-plane halo,
+    // dt^2 v^2 and u^{n-1}.  Three register sets rotate so that the loads of
+    // plane z+2 are in flight while plane z is computed (two planes ahead);
+    // the loop is unrolled by three so the rotation needs no register moves,
+    // which would otherwise wait for the loads they move.
+    struct PlaneRegs {
+        float4 front, pv, mv;
+        float4 hv[HPT];
+    };
+    auto issue = [&](PlaneRegs &r, int zz) {
+        zz = min(zz, z1 - 1);   // past the chunk: a harmless in-bounds reload
+        const long long zo = (long long)zz * plane;
+        r.front = E::ld4(U + base + zo + (long long)R * plane);
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) hv[k] = E::ld4(U + hoff[k] + (long long)z0 * plane);
-    float4 pv = *reinterpret_cast<const float4 *>(Pp + base + (long long)z0 * plane);
-    float4 mv = E::ld4(Pv + base + (long long)z0 * plane);
-
-    for (int z = z0; z < z1; ++z) {
+        for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4(U + hoff[k] + zo);
+        r.pv = *reinterpret_cast<const float4 *>(Pp + base + zo);
+        r.mv = E::ld4(Pv + base + zo);
+    };
+    auto body = [&](int z, const PlaneRegs &cur, PlaneRegs &ahead) {
         float4 *buf = lds[(z - z0) & 1];
-        q[2 * R] = front;
+        q[2 * R] = cur.front;
         buf[(R + ty) * W4 + HX4 + tx] = q[R];
 #pragma unroll
         for (int k = 0; k < HPT; ++k)
-            if (hl[k] >= 0) buf[hl[k]] = hv[k];
-        const float4 pc = pv, mc = mv;
-        if (z + 1 < z1) {
-            const long long zo = (long long)(z + 1) * plane;
-            front = E::ld4(U + base + zo + (long long)R * plane);
-#pragma unroll
-            for (int k = 0; k < HPT; ++k) hv[k] = E::ld4(U + hoff[k] + zo);
-            pv = *reinterpret_cast<const float4 *>(Pp + base + zo);
-            mv = E::ld4(Pv + base + zo);
-        }
+            if (hl[k] >= 0) buf[hl[k]] = cur.hv[k];
+        issue(ahead, z + 2);
         __syncthreads();
 
         if (active) {
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             float un[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                un[i] = update_point(comp(q[R], i), comp(mc, i), comp(pc, i), lap[i], src[i],
+                un[i] = update_point(comp(q[R], i), comp(cur.mv, i), comp(cur.pv, i), lap[i], src[i],
                                      sxy[i] + sz);
             const long long off = base + (long long)z * plane;
             const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
@@ -315,7 +318,19 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         }
 #pragma unroll
         for (int k = 0; k < 2 * R; ++k) q[k] = q[k + 1];
+    };
+
+    PlaneRegs s0, s1, s2;
+    issue(s0, z0);
+    issue(s1, z0 + 1);
+    int z = z0;
+    for (; z + 3 <= z1; z += 3) {
+        body(z, s0, s2);
+        body(z + 1, s1, s0);
+        body(z + 2, s2, s1);
     }
+    if (z < z1) body(z, s0, s2);
+    if (z + 1 < z1) body(z + 1, s1, s0);
 }
 
 // ------------------------------------------------------------------ 2D step
@@ -608,6 +623,26 @@ hipError_t launch_step(const StepArgs &a, Store st, bool imaging, hipStream_t s)
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(f, dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+int step_blocks_per_cu(int ndim, int r, Store st, bool imaging) {
+    StepFn f = nullptr;
+    if (imaging) {
+        if (st != Store::F32) return 0;
+        f = pick<Store::F32, true>(ndim, r);
+    } else {
+        switch (st) {
+            case Store::F32: f = pick<Store::F32, false>(ndim, r); break;
+            case Store::F16: f = pick<Store::F16, false>(ndim, r); break;
+            case Store::BF16: f = pick<Store::BF16, false>(ndim, r); break;
+        }
+    }
+    if (!f) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(f), kBlock, 0) !=
+        hipSuccess)
+        return 0;
+    return n;
 }
 
 hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s) {
