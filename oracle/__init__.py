@@ -22,7 +22,9 @@ listed with its pin in the design notes:
   O2 medium      v on the padded grid, layer filled by edge replication.
   O3 weights     maximal-order central 2nd-derivative weights, r = so/2.
   O4 Laplacian   sum over axes, zero outside the padded grid.
-  O5 damping     sigma = sigma_max sum_a (d_a / nbl)^2.
+  O5 damping     sigma = sigma_max sum_a (d_a / nbl)^2  (parity unpinned:
+                 the profile itself has no pin, only invariants that hold
+                 for any sigma >= 0).
   O6 update      centred leapfrog with centred damping.
   O7 time step   Courant number v_max dt / h.
   O8 sources     multilinear weights over the 2^d cell corners, / prod(h).
@@ -178,7 +180,9 @@ def pad_velocity(g: Grid, v_phys) -> np.ndarray:
 
 
 def sigma_max_default(g: Grid, vmax: float) -> float:
-    """O5 default: 3 v_max ln(1000) / (2 nbl h), h the smallest spacing."""
+    """O5 default: 3 v_max ln(1000) / (2 nbl h), h the smallest spacing.
+    Parity unpinned: the thesis describes no absorbing layer; this value is a
+    reading, checked only through invariants that hold for any sigma >= 0."""
     if g.nbl == 0:
         return 0.0
     return 3.0 * vmax * math.log(1000.0) / (2.0 * g.nbl * min(g.spacing))
@@ -186,7 +190,10 @@ def sigma_max_default(g: Grid, vmax: float) -> float:
 
 def damping(g: Grid, sigma_max: float) -> np.ndarray:
     """O5: sigma_i = sigma_max sum_a (d_a / nbl)^2 with
-    d_a = max(0, nbl - i_a, i_a - (nbl + N_a - 1)); zero when nbl == 0."""
+    d_a = max(0, nbl - i_a, i_a - (nbl + N_a - 1)); zero when nbl == 0.
+    Parity unpinned: no passage of the thesis fixes the profile; the pins
+    that cover it (energy non-increasing, reciprocity, adjoint identity,
+    gradient in the layer) hold for any non-negative profile."""
     sig = np.zeros(g.array_shape, dtype=np.float64)
     if g.nbl == 0:
         return sig

@@ -53,7 +53,9 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        jobs.append([hipcc] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj])
+        # host-only translation units: no device pass
+        jobs.append([hipcc] + COMMON + ["-x", "hip", "--cuda-host-only", "--offload-arch=" + ARCH, "-c",
+                                        os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=min(4, len(jobs))) as ex:
         for r in ex.map(_run, jobs):

@@ -557,6 +557,10 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
             const int tiles = g->ntx * g->nty;
             const int nzc = std::max(1, std::min(L.nz, occ * cus / std::max(1, tiles)));
             zc = (L.nz + nzc - 1) / nzc;
+            // Wide xy planes leave few chunks per round; long chunks then
+            // lose more to the round tail than short ones lose to their
+            // 2r warm-up planes (measured: 592^3, so 8).
+            if (zc > 128) zc = 64;
         }
         g->zchunk = std::min(std::min(zc, L.nz), kMaxChunk);
         g->ntz = (L.nz + g->zchunk - 1) / g->zchunk;

@@ -29,12 +29,37 @@ namespace fd {
 namespace {
 
 // ------------------------------------------------------------ storage types
+// ld4/st4 move 4 consecutive points.  The *nt forms carry the non-temporal
+// hint: u^{n-1}, dt^2 v^2 and u^{n+1} are each touched once per step, so
+// streaming them past the caches leaves L2 to the centre field, whose
+// planes are re-read as halo by the neighbouring tiles.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline float4 ld4nt_f32(const float *p) {
+    const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ inline void st4nt_f32(float *p, float4 v) {
+    const f32x4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, reinterpret_cast<f32x4 *>(p));
+}
+__device__ inline uint2 ld2nt_u32(const uint16_t *p) {
+    const u32x2 t = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+    return make_uint2(t.x, t.y);
+}
+__device__ inline void st2nt_u32(uint16_t *p, uint2 v) {
+    const u32x2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<u32x2 *>(p));
+}
+
 template <Store S> struct Elem;
 
 template <> struct Elem<Store::F32> {
     using T = float;
     __device__ static float4 ld4(const T *p) { return *reinterpret_cast<const float4 *>(p); }
-    __device__ static void st4(T *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+    __device__ static float4 ld4nt(const T *p) { return ld4nt_f32(p); }
+    __device__ static void st4nt(T *p, float4 v) { st4nt_f32(p, v); }
     __device__ static float ld(const T *p) { return *p; }
     __device__ static void st(T *p, float v) { *p = v; }
 };
@@ -49,37 +74,32 @@ __device__ inline uint16_t f2b(float f) {
     return (uint16_t)(u >> 16);
 }
 
-template <> struct Elem<Store::F16> {
+template <typename Cvt> struct Elem16 {
     using T = uint16_t;
-    __device__ static float4 ld4(const T *p) {
-        uint2 v = *reinterpret_cast<const uint2 *>(p);
-        return make_float4(h2f(v.x & 0xFFFF), h2f(v.x >> 16), h2f(v.y & 0xFFFF), h2f(v.y >> 16));
+    __device__ static float4 unpack(uint2 v) {
+        return make_float4(Cvt::to_f(v.x & 0xFFFF), Cvt::to_f(v.x >> 16), Cvt::to_f(v.y & 0xFFFF),
+                           Cvt::to_f(v.y >> 16));
     }
-    __device__ static void st4(T *p, float4 v) {
-        uint2 o;
-        o.x = (uint32_t)f2h(v.x) | ((uint32_t)f2h(v.y) << 16);
-        o.y = (uint32_t)f2h(v.z) | ((uint32_t)f2h(v.w) << 16);
-        *reinterpret_cast<uint2 *>(p) = o;
+    __device__ static uint2 pack(float4 v) {
+        return make_uint2((uint32_t)Cvt::from_f(v.x) | ((uint32_t)Cvt::from_f(v.y) << 16),
+                          (uint32_t)Cvt::from_f(v.z) | ((uint32_t)Cvt::from_f(v.w) << 16));
     }
-    __device__ static float ld(const T *p) { return h2f(*p); }
-    __device__ static void st(T *p, float v) { *p = f2h(v); }
+    __device__ static float4 ld4(const T *p) { return unpack(*reinterpret_cast<const uint2 *>(p)); }
+    __device__ static float4 ld4nt(const T *p) { return unpack(ld2nt_u32(p)); }
+    __device__ static void st4nt(T *p, float4 v) { st2nt_u32(p, pack(v)); }
+    __device__ static float ld(const T *p) { return Cvt::to_f(*p); }
+    __device__ static void st(T *p, float v) { *p = Cvt::from_f(v); }
 };
-
-template <> struct Elem<Store::BF16> {
-    using T = uint16_t;
-    __device__ static float4 ld4(const T *p) {
-        uint2 v = *reinterpret_cast<const uint2 *>(p);
-        return make_float4(b2f(v.x & 0xFFFF), b2f(v.x >> 16), b2f(v.y & 0xFFFF), b2f(v.y >> 16));
-    }
-    __device__ static void st4(T *p, float4 v) {
-        uint2 o;
-        o.x = (uint32_t)f2b(v.x) | ((uint32_t)f2b(v.y) << 16);
-        o.y = (uint32_t)f2b(v.z) | ((uint32_t)f2b(v.w) << 16);
-        *reinterpret_cast<uint2 *>(p) = o;
-    }
-    __device__ static float ld(const T *p) { return b2f(*p); }
-    __device__ static void st(T *p, float v) { *p = f2b(v); }
+struct CvtF16 {
+    __device__ static float to_f(uint32_t h) { return h2f((uint16_t)h); }
+    __device__ static uint16_t from_f(float f) { return f2h(f); }
 };
+struct CvtBF16 {
+    __device__ static float to_f(uint32_t b) { return b2f((uint16_t)b); }
+    __device__ static uint16_t from_f(float f) { return f2b(f); }
+};
+template <> struct Elem<Store::F16> : Elem16<CvtF16> {};
+template <> struct Elem<Store::BF16> : Elem16<CvtBF16> {};
 
 __device__ inline float comp(const float4 &v, int i) {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
@@ -227,31 +247,51 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) q[k] = E::ld4(U + base + (long long)(z0 - R + k) * plane);
 
-    // Loads of one plane: the queue front u(z+R), the staged-plane halo,
+    // Halo ring: each lane keeps the halo items it loads in R+1 LDS slots.
+    // A halo row of plane z belongs to a neighbour tile, which streams plane
+    // z as its queue front R planes before this tile stages plane z; loading
+    // the halo at that same time lets the neighbour's fetch serve it from L2.
+    constexpr int kRing = R + 1;
+    __shared__ float4 ring[kRing * NH];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < HPT; ++k)
+            if (hl[k] >= 0) ring[i * NH + lane + k * kBlock] = E::ld4(U + hoff[k] + (long long)(z0 + i) * plane);
+
+    // Loads for plane z: the queue front u(z+R), the halo of plane z+R,
     // dt^2 v^2 and u^{n-1}.  Three register sets rotate so that the loads of
     // plane z+2 are in flight while plane z is computed (two planes ahead);
     // the loop is unrolled by three so the rotation needs no register moves,
     // which would otherwise wait for the loads they move.
     struct PlaneRegs {
         float4 front, pv, mv;
-        float4 hv[HPT];
+        float4 hv[HPT];   // halo of plane z+R
     };
     auto issue = [&](PlaneRegs &r, int zz) {
         zz = min(zz, z1 - 1);   // past the chunk: a harmless in-bounds reload
         const long long zo = (long long)zz * plane;
         r.front = E::ld4(U + base + zo + (long long)R * plane);
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4(U + hoff[k] + zo);
-        r.pv = *reinterpret_cast<const float4 *>(Pp + base + zo);
-        r.mv = E::ld4(Pv + base + zo);
+        for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4(U + hoff[k] + zo + (long long)R * plane);
+        r.pv = ld4nt_f32(Pp + base + zo);
+        r.mv = E::ld4nt(Pv + base + zo);
     };
     auto body = [&](int z, const PlaneRegs &cur, PlaneRegs &ahead) {
         float4 *buf = lds[(z - z0) & 1];
         q[2 * R] = cur.front;
         buf[(R + ty) * W4 + HX4 + tx] = q[R];
+        // park the halo of plane z+R (fetched with the front of the same
+        // plane) and stage the halo of plane z parked R planes ago
+        float4 *ring_w = ring + ((z - z0 + R) % kRing) * NH + lane;
+        const float4 *ring_r = ring + ((z - z0) % kRing) * NH + lane;
 #pragma unroll
-        for (int k = 0; k < HPT; ++k)
-            if (hl[k] >= 0) buf[hl[k]] = cur.hv[k];
+        for (int k = 0; k < HPT; ++k) {
+            if (hl[k] >= 0) {
+                ring_w[k * kBlock] = cur.hv[k];
+                buf[hl[k]] = ring_r[k * kBlock];
+            }
+        }
         issue(ahead, z + 2);
         __syncthreads();
 
@@ -295,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
             const int nvalid = L.nx - x;
             if (nvalid >= 4) {
-                E::st4(O + off, r4);
+                E::st4nt(O + off, r4);
             } else {
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
@@ -413,8 +453,8 @@ __global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
         const int e0 = s_pp[z - z0], e1 = s_pp[z - z0 + 1];
         if (e0 < e1) gather_sources(a.inj, e0, e1, x, 0, src[0], src[1], src[2], src[3]);
         const long long off = L.offset(x, 0, z);
-        const float4 pc = *reinterpret_cast<const float4 *>(a.p + off);
-        const float4 mc = E::ld4(Pv + off);
+        const float4 pc = ld4nt_f32(a.p + off);
+        const float4 mc = E::ld4nt(Pv + off);
         const float4 cc = row[0];
         const float sz = s_dz[z - z0];
         float un[4];
@@ -422,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
         for (int i = 0; i < 4; ++i)
             un[i] = update_point(comp(cc, i), comp(mc, i), comp(pc, i), lap[i], src[i], sx[i] + sz);
         if (nvalid >= 4) {
-            E::st4(O + off, make_float4(un[0], un[1], un[2], un[3]));
+            E::st4nt(O + off, make_float4(un[0], un[1], un[2], un[3]));
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
