@@ -177,9 +177,15 @@ def bench_gradient(torch, dev, stream):
         e1.record(stream)
     torch.cuda.synchronize()
     secs = e0.elapsed_time(e1) / 1000.0 / reps
-    out = dict(workload="gradient3d_200", gpts=g.padded_points * w["nt"] / secs / 1e9,
-               ms=secs * 1000.0, misfit=float(mis.item()), checkpoint_every=w["checkpoint_every"],
-               b_alg_per_pt=80)
+    # algorithmic bytes per point and time step: forward 16, recompute 16 +
+    # bracket write 4, adjoint 16 + bracket read 4 + FP64 accumulate 16, and
+    # two field copies (read + write) per checkpoint and per segment restore
+    K = w["checkpoint_every"]
+    b_alg = 72.0 + 32.0 / K
+    gpts = g.padded_points * w["nt"] / secs / 1e9
+    out = dict(workload="gradient3d_200", gpts=gpts, ms=secs * 1000.0, misfit=float(mis.item()),
+               checkpoint_every=K, b_alg_per_pt=b_alg, achieved_gbs=gpts * b_alg,
+               frac_hbm=gpts * b_alg / HBM_PEAK_GBS)
     g.close()
     return out
 
@@ -247,13 +253,47 @@ def bench_serving(torch, n=24, budget_gib=8.0, slots=6):
                 peak_bytes=st["peak_bytes"], peak_slots=st["peak_slots"])
 
 
+def bench_diffusion(torch, dev, stream):
+    """The thesis's own benchmark (Section 5.1.2): 2D diffusion, nu = 0.5,
+    first order in time, FP32, 1000 steps, grids 2500^2 and 10000^2, space
+    orders 2..12.  Algorithmic bytes: read u^n, write u^{n+1} = 8 B/point."""
+    from paper_1906_10811_amd import diffusion
+    out = {}
+    for n in (2500, 10000):
+        h = 1.0 / (n - 1)
+        u0 = torch.ones((n, n), dtype=torch.float32, device=dev)
+        u0[n // 4: n // 2, n // 4: n // 2] = 2.0
+        res = torch.empty_like(u0)
+        for so in (2, 4, 8, 12):
+            r = so // 2
+            c = [0.0] * (r + 1)
+            for j in range(1, r + 1):
+                c[j] = 2 * (-1) ** (j + 1) * math.factorial(r) ** 2 / (j * j * math.factorial(r - j) * math.factorial(r + j))
+            s_odd = sum(c[j] for j in range(1, r + 1, 2))
+            dt = 0.8 / (2.0 * s_odd * 2.0 / h ** 2) / 0.5
+            diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                e0.record(stream)
+                diffusion(u0, (h, h), so, 0.5, dt, 1000, out=res, stream=stream)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            secs = e0.elapsed_time(e1) / 1000.0
+            gpts = n * n * 1000 / secs / 1e9
+            out["%d^2 so%d" % (n, so)] = dict(gpts=round(gpts, 1), frac_hbm=round(gpts * 8.0 / HBM_PEAK_GBS, 4))
+        del u0, res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extras", default="all", help="comma list of gradient,precision,serving or all/none")
+    ap.add_argument("--extras", default="all", help="comma list of gradient,precision,serving,diffusion or all/none")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box in this setup has a single MI355X, and the "
@@ -267,7 +307,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
     extras = set(args.extras.split(",")) if args.extras not in ("all", "none") else (
-        {"gradient", "precision", "serving"} if args.extras == "all" else set())
+        {"gradient", "precision", "serving", "diffusion"} if args.extras == "all" else set())
 
     copy_gbs = copy_probe(torch, dev, stream)
     log("stream copy: %.0f GB/s" % copy_gbs)
@@ -310,6 +350,9 @@ def main():
     if "gradient" in extras:
         log("gradient: gradient3d_200")
         line["gradient"] = bench_gradient(torch, dev, stream)
+    if "diffusion" in extras:
+        log("diffusion (2D, the thesis's benchmark)")
+        line["diffusion2d"] = bench_diffusion(torch, dev, stream)
     if "serving" in extras:
         log("serving")
         line["serving"] = bench_serving(torch)

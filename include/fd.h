@@ -80,7 +80,8 @@ typedef struct fd_grid_desc {
     int nbl;               /* damping-layer points added on every face, >= 0 */
     double damp_max;       /* sigma_max in 1/s; <= 0 selects 3 v_max ln(1000) / (2 nbl h_min) */
     int storage;           /* fd_storage */
-    float amp_scale;       /* 16-bit storage keeps amp_scale * u; 0 selects 1 */
+    float amp_scale;       /* 16-bit storage keeps amp_scale * u; 0 selects 1 for BF16 and,
+                              for F16, the power of two nearest prod(h)/(dt^2 v_max^2) */
     int vp_padded;         /* 0: vp given on the physical grid, layer filled by edge
                               replication; 1: vp given on the padded grid */
     int max_src;           /* capacity of the source table (points), 0 selects 64 */
@@ -233,6 +234,33 @@ int fd_request_bytes(const fd_request *req, size_t *bytes);
 int fd_server_stats(fd_server *srv, size_t *peak_bytes, int *peak_slots);
 /* Finish all queued work, then release the arena. */
 int fd_server_destroy(fd_server *srv);
+
+/* ---------------------------------------------------------------- diffusion
+ * The problem the thesis benchmarks (Section 5.1.2): u_t = nu (u_xx + u_yy)
+ * on a 2D grid, first order in time,
+ *   u^{n+1} = u^n + nu dt Lap_h u^n,
+ * with the same space-order-so weights and zero extension as above.  The
+ * so-2 case is the printed kernel of Sections 3.2.2 and 5.1.5.
+ */
+typedef struct fd_diffusion_desc {
+    int shape[2];          /* points (x, y), each >= 2 */
+    double spacing[2];     /* h_x, h_y > 0 */
+    int space_order;       /* even, 2..16 */
+    double nu;             /* diffusivity > 0 */
+} fd_diffusion_desc;
+
+/* Device workspace for fd_diffusion_run (two pitched float32 fields). */
+int fd_diffusion_workspace_bytes(const fd_diffusion_desc *desc, size_t *bytes);
+
+/*
+ * nt explicit steps from u0_dev (device float32, dense [Ny][Nx]) into
+ * u_out_dev (device float32, dense, may alias u0_dev).  workspace: >= the
+ * size above, 256-byte aligned, used during the call only.  FD_ERR_UNSTABLE
+ * if nu dt exceeds the explicit limit 1 / (2 sum_{j odd} c_j sum_a h_a^-2).
+ * Enqueues on `stream` and returns.
+ */
+int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, size_t ws_bytes,
+                     const float *u0_dev, float *u_out_dev, int nt, double dt, void *stream);
 
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *fd_last_error(void);

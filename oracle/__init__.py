@@ -380,3 +380,30 @@ def energy(g: Grid, v_pad, dt: float, u_next, u_cur) -> float:
     m = 1.0 / np.asarray(v_pad, dtype=np.float64) ** 2
     du = (np.asarray(u_next) - np.asarray(u_cur)) / dt
     return float(np.sum(m * du * du) - np.sum(np.asarray(u_next) * laplacian(g, u_cur)))
+
+
+# --------------------------------------------------------------------------
+# The thesis's benchmark problem: 2D diffusion (Section 5.1.2)
+# --------------------------------------------------------------------------
+def diffusion(g: Grid, u0, nu: float, dt: float, nt: int) -> np.ndarray:
+    """Explicit diffusion u_t = nu (u_xx + u_yy), first order in time: the
+    operator Section 5.1.2 benchmarks (solve(Eq(u.dt, nu*(u.dx2 + u.dy2)),
+    u.forward)), u^{n+1} = u^n + nu dt Lap_h u^n with the O3 weights and the
+    field zero outside the grid.  Returns u^{nt}."""
+    if g.ndim != 2 or g.nbl != 0:
+        raise ValueError("diffusion is defined on a 2D grid without damping layer")
+    u = np.array(u0, dtype=np.float64, copy=True)
+    if u.shape != g.array_shape:
+        raise ValueError("field shape")
+    for _ in range(int(nt)):
+        u = u + nu * dt * laplacian(g, u)
+    return u
+
+
+def diffusion_critical_dt(g: Grid, nu: float) -> float:
+    """Stability limit of the explicit diffusion step: the largest
+    eigenvalue of -Lap_h is 4 sum_{j odd} c_j sum_a h_a^-2, and the forward
+    Euler factor 1 - nu dt lambda must stay >= -1."""
+    c = fd_weights_exact(g.space_order)
+    s_odd = float(sum(c[j] for j in range(1, len(c)) if j % 2 == 1))
+    return 2.0 / (nu * 4.0 * s_odd * sum(1.0 / h ** 2 for h in g.spacing))

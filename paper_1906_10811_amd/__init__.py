@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import FDError  # noqa: F401
 
-__all__ = ["Grid", "Server", "FDError", "modeling", "build"]
+__all__ = ["Grid", "Server", "FDError", "modeling", "diffusion", "build"]
 
 _STORAGE = {"f32": _lib.FD_STORE_F32, "f16": _lib.FD_STORE_F16, "bf16": _lib.FD_STORE_BF16}
 
@@ -329,3 +329,28 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def diffusion(u0: torch.Tensor, spacing, space_order: int, nu: float, dt: float, nt: int,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """fd_diffusion_run: nt explicit steps of u_t = nu (u_xx + u_yy) from the
+    CUDA float32 field u0 [Ny, Nx]; returns u^nt (a new tensor unless `out`)."""
+    lib = _lib.load()
+    u = _dev_f32(u0, "u0")
+    if u.dim() != 2:
+        raise ValueError("u0 must be [Ny, Nx]")
+    d = _lib.DiffusionDesc()
+    d.shape[0], d.shape[1] = int(u.shape[1]), int(u.shape[0])
+    d.spacing[0], d.spacing[1] = float(spacing[0]), float(spacing[1])
+    d.space_order = int(space_order)
+    d.nu = float(nu)
+    nbytes = ctypes.c_size_t()
+    _lib.check(lib.fd_diffusion_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=u.device)
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    res = out if out is not None else torch.empty_like(u)
+    _lib.check(lib.fd_diffusion_run(ctypes.byref(d), ctypes.c_void_p(aligned), nbytes.value,
+                                    ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(res.data_ptr()),
+                                    int(nt), float(dt), _stream_ptr(stream)))
+    ws.record_stream(torch.cuda.current_stream() if stream is None else stream)
+    return res

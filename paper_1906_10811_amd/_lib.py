@@ -29,7 +29,7 @@ EXPORTS = (
     "fd_grid_workspace_bytes", "fd_grid_create", "fd_grid_destroy", "fd_grid_get_info",
     "fd_forward", "fd_adjoint", "fd_gradient_workspace_bytes", "fd_gradient",
     "fd_server_create", "fd_submit", "fd_wait", "fd_request_bytes", "fd_server_stats",
-    "fd_server_destroy", "fd_last_error",
+    "fd_server_destroy", "fd_last_error", "fd_diffusion_workspace_bytes", "fd_diffusion_run",
 )
 
 
@@ -116,6 +116,15 @@ class Result(ctypes.Structure):
     ]
 
 
+class DiffusionDesc(ctypes.Structure):
+    _fields_ = [
+        ("shape", ctypes.c_int * 2),
+        ("spacing", ctypes.c_double * 2),
+        ("space_order", ctypes.c_int),
+        ("nu", ctypes.c_double),
+    ]
+
+
 class FDError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("libfd error %d: %s" % (code, msg))
@@ -152,6 +161,8 @@ def load() -> ctypes.CDLL:
         "fd_server_stats": (I, [P, PS, ctypes.POINTER(ctypes.c_int)]),
         "fd_server_destroy": (I, [P]),
         "fd_last_error": (ctypes.c_char_p, []),
+        "fd_diffusion_workspace_bytes": (I, [ctypes.POINTER(DiffusionDesc), PS]),
+        "fd_diffusion_run": (I, [ctypes.POINTER(DiffusionDesc), P, S, P, P, I, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

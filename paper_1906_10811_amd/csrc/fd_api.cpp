@@ -230,9 +230,11 @@ struct fd_grid {
     char *stage;
     hipEvent_t stage_ev;
     bool stage_pending;
-    int ntx, nty, ntz, zchunk;
+    int ntx, nty;
+    int ntz[3], zchunk[3];   // per step mode (kPlain, kBracket, kImage)
     hipStream_t last_stream;   // stream of the latest enqueued work
     bool has_last_stream;
+    bool auto_amp;             // F16 storage with the scale chosen per dt
 };
 
 namespace {
@@ -258,8 +260,14 @@ inline void note_stream(fd_grid *g, hipStream_t s) {
 }
 
 // Damping tables sigma_a(i) dt / 2 = damp_max (d_a/nbl)^2 dt / 2 and p = dt^2 v^2.
+// F16 storage without a caller scale: the stored field is 2^k u with 2^k
+// about prod(h) / (dt^2 v_max^2), the inverse of what a unit source puts in
+// its cell in one step, so near-source values sit near 1 and the far field
+// stays in half precision's normal range (>= 6.1e-5) down to 1e-4 of that.
 int ensure_dt(fd_grid *g, double dt, hipStream_t s) {
     if (g->dt_cached == dt) return FD_OK;
+    if (g->auto_amp)
+        g->amp = (float)std::exp2(std::round(std::log2(g->cell / (dt * dt * g->vmax * g->vmax))));
     const Layout &L = g->L;
     int rc = stage_acquire(g);
     if (rc) return rc;
@@ -417,8 +425,8 @@ StepArgs base_args(const fd_grid *g) {
     }
     a.ntx = g->ntx;
     a.nty = g->nty;
-    a.ntz = g->ntz;
-    a.zchunk = g->zchunk;
+    a.ntz = g->ntz[kPlain];
+    a.zchunk = g->zchunk[kPlain];
     return a;
 }
 
@@ -496,6 +504,7 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     g->L = L;
     g->st = (Store)desc->storage;
     g->amp = (desc->storage != FD_STORE_F32 && desc->amp_scale > 0.f) ? desc->amp_scale : 1.f;
+    g->auto_amp = desc->storage == FD_STORE_F16 && !(desc->amp_scale > 0.f);
     g->nc = 1 << desc->ndim;
     second_derivative_weights(L.r, g->c);
     g->cell = 1.0;
@@ -540,10 +549,16 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     if (hipHostMalloc((void **)&g->stage, wp.stage_bytes, hipHostMallocDefault) != hipSuccess)
         return cleanup(fdi_fail(FD_ERR_NOMEM, "pinned staging allocation failed"));
 
-    // launch geometry
-    if (desc->ndim == 3) {
-        g->ntx = (L.nx + kTileX - 1) / kTileX;
-        g->nty = (L.ny + kTileY - 1) / kTileY;
+    // launch geometry of each step mode (the gradient modes differ in
+    // register use, hence occupancy, hence chunking)
+    g->ntx = (L.nx + kTileX - 1) / kTileX;
+    g->nty = desc->ndim == 3 ? (L.ny + kTileY - 1) / kTileY : 1;
+    for (int m = 0; m < 3; ++m) {
+        if (desc->ndim == 2) {
+            g->zchunk[m] = kTile2Z;
+            g->ntz[m] = (L.nz + kTile2Z - 1) / kTile2Z;
+            continue;
+        }
         int zc = desc->zchunk;
         if (zc <= 0) {
             // One round of workgroups: as many z chunks per xy tile as the
@@ -553,7 +568,7 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
                 cus <= 0)
                 cus = 256;
-            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, false));
+            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m));
             const int tiles = g->ntx * g->nty;
             const int nzc = std::max(1, std::min(L.nz, occ * cus / std::max(1, tiles)));
             zc = (L.nz + nzc - 1) / nzc;
@@ -562,13 +577,8 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
             // 2r warm-up planes (measured: 592^3, so 8).
             if (zc > 128) zc = 64;
         }
-        g->zchunk = std::min(std::min(zc, L.nz), kMaxChunk);
-        g->ntz = (L.nz + g->zchunk - 1) / g->zchunk;
-    } else {
-        g->ntx = (L.nx + kTileX - 1) / kTileX;
-        g->nty = 1;
-        g->ntz = (L.nz + kTile2Z - 1) / kTile2Z;
-        g->zchunk = kTile2Z;
+        g->zchunk[m] = std::min(std::min(zc, L.nz), kMaxChunk);
+        g->ntz[m] = (L.nz + g->zchunk[m] - 1) / g->zchunk[m];
     }
 
     // zero every field (halos included), fill velocity, find v_max
@@ -670,7 +680,7 @@ int fdi_forward_steps(fd_grid *g, const fd_shot *sh, int nt, int n0, int n1, flo
         a.smp = make_sample(g, 1, sh->nrec, (rec_out && n >= 1) ? rec_out + (size_t)(n - 1) * sh->nrec : nullptr,
                             smp_scale);
         a.nsamp_blocks = samp_blocks(a.smp);
-        HIPCHK(launch_step(a, g->st, false, s));
+        HIPCHK(launch_step(a, g->st, kPlain, s));
         std::swap(A, B);
     }
     if (rec_out && n1 == nt && nt >= 1) {
@@ -753,7 +763,7 @@ extern "C" int fd_adjoint(fd_grid *g, const fd_shot *sh, int nt, double dt,
         a.inj = make_inject(g, 1, residual + (size_t)(k - 1) * sh->nrec, inj_scale);
         a.smp = make_sample(g, 0, sh->nsrc, k <= nt - 1 ? src_adj + (size_t)k * sh->nsrc : nullptr, smp_scale);
         a.nsamp_blocks = samp_blocks(a.smp);
-        HIPCHK(launch_step(a, g->st, false, s));
+        HIPCHK(launch_step(a, g->st, kPlain, s));
         std::swap(A, B);
     }
     if (nt >= 1) {
@@ -765,18 +775,24 @@ extern "C" int fd_adjoint(fd_grid *g, const fd_shot *sh, int nt, double dt,
 }
 
 namespace {
+// Gradient workspace: 2 checkpoint fields every K steps, the two rotating
+// fields of the segment recompute, K imaging brackets (float32 fields), the
+// float64 accumulator in the pitched layout, traces and residual.
 struct GradPlan {
-    size_t ckpt, seg, rec, resid, total;
-    int ncp, K;
+    size_t ckpt, rot, br, grad, rec, resid, total;
+    int ncp, K, nbr;
 };
 GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K) {
     GradPlan p{};
     p.K = K;
     p.ncp = (nt + K - 1) / K;
+    p.nbr = std::min(K, nt);
     const size_t fb = g->wp.field_bytes;
     size_t o = 0;
     p.ckpt = o; o += fb * 2 * (size_t)p.ncp;
-    p.seg = o; o += fb * (size_t)(std::min(K, nt) + 2);
+    p.rot = o; o += fb * 2;
+    p.br = o; o += fb * (size_t)p.nbr;
+    p.grad = o; o = align_up(o + sizeof(double) * (size_t)g->L.elems, 256);
     p.rec = o; o = align_up(o + sizeof(float) * (size_t)nt * nrec, 256);
     p.resid = o; o = align_up(o + sizeof(float) * (size_t)nt * nrec, 256);
     p.total = o;
@@ -818,11 +834,10 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     const size_t fb = g->wp.field_bytes;
     std::vector<void *> ck((size_t)2 * gp.ncp);
     for (int i = 0; i < 2 * gp.ncp; ++i) ck[i] = ws + gp.ckpt + fb * (size_t)i;
-    const int nslot = std::min(K, nt) + 2;
-    std::vector<void *> slot(nslot);
-    for (int i = 0; i < nslot; ++i) slot[i] = ws + gp.seg + fb * (size_t)i;
-    // recompute slots are written on data points only: their halos must read zero
-    for (int i = 2; i < nslot; ++i) HIPCHK(launch_zero_field(L, slot[i], g->st, s));
+    void *rotA = ws + gp.rot, *rotB = ws + gp.rot + fb;
+    std::vector<float *> br(gp.nbr);
+    for (int i = 0; i < gp.nbr; ++i) br[i] = (float *)(ws + gp.br + fb * (size_t)i);
+    double *gacc = (double *)(ws + gp.grad);
     float *recb = (float *)(ws + gp.rec);
     float *resid = (float *)(ws + gp.resid);
 
@@ -834,8 +849,10 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     const long long nres = (long long)nt * sh->nrec;
     HIPCHK(launch_misfit(recb, d_obs, nres, (flags & FD_GRAD_RESIDUAL_GIVEN) ? 1 : 0, resid,
                          g->partials, kNPart, misfit, s));
-    // 3. adjoint sweep over segments, last to first, recomputing each segment
-    HIPCHK(launch_zero_f64(grad_m, (long long)L.nx * L.ny * L.nz, s));
+    // 3. adjoint sweep over segments, last to first.  Each segment is
+    //    recomputed from its checkpoint, writing the imaging bracket of every
+    //    time level; the adjoint steps then read one bracket per point.
+    HIPCHK(launch_zero_f64(gacc, L.elems, s));
     HIPCHK(launch_zero_field(L, g->uA, g->st, s));
     HIPCHK(launch_zero_field(L, g->uB, g->st, s));
     void *LA = g->uA, *LB = g->uB;   // lambda^k, lambda^{k+1}
@@ -843,21 +860,25 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     const float fwd_inj = (float)(1.0 / g->cell);
     const float adj_inj = (float)(1.0 / (dt * dt));
     const float adj_smp = (float)(dt * dt / g->cell);
-    const int nseg = gp.ncp;
-    for (int seg = nseg - 1; seg >= 0; --seg) {
+    for (int seg = gp.ncp - 1; seg >= 0; --seg) {
         const int c = seg * K;
         const int e = std::min(c + K, nt);
-        HIPCHK(hipMemcpyAsync(slot[0], ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(slot[1], ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
-        for (int i = 0; i < e - c; ++i) {
-            a.u = slot[i + 1];
-            a.prev = slot[i];
-            a.out = slot[i + 2];
-            a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)(c + i) * sh->nsrc, fwd_inj);
+        HIPCHK(hipMemcpyAsync(rotA, ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(rotB, ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
+        void *A = rotA, *B = rotB;   // u^n, u^{n-1}
+        for (int n = c; n < e; ++n) {
+            a.u = A;
+            a.prev = B;
+            a.out = B;
+            a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, fwd_inj);
             a.smp = Sample{};
             a.nsamp_blocks = 0;
             a.img = Imaging{};
-            HIPCHK(launch_step(a, g->st, false, s));
+            a.img.br_out = br[n - c];
+            a.ntz = g->ntz[kBracket];
+            a.zchunk = g->zchunk[kBracket];
+            HIPCHK(launch_step(a, g->st, kBracket, s));
+            std::swap(A, B);
         }
         for (int k = e; k >= c + 1; --k) {
             a.u = LA;
@@ -867,14 +888,16 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
             a.smp = make_sample(g, 0, sh->nsrc, (src_adj && k <= nt - 1) ? src_adj + (size_t)k * sh->nsrc : nullptr,
                                 adj_smp);
             a.nsamp_blocks = samp_blocks(a.smp);
-            a.img.u1 = slot[k - c + 1];
-            a.img.u0 = slot[k - c];
-            a.img.um = slot[k - c - 1];
-            a.img.grad = grad_m;
-            HIPCHK(launch_step(a, g->st, true, s));
+            a.img = Imaging{};
+            a.img.br_in = br[k - 1 - c];
+            a.img.grad = gacc;
+            a.ntz = g->ntz[kImage];
+            a.zchunk = g->zchunk[kImage];
+            HIPCHK(launch_step(a, g->st, kImage, s));
             std::swap(LA, LB);
         }
     }
+    HIPCHK(launch_field_to_dense_f64(L, gacc, grad_m, s));
     if (src_adj) {
         Sample sm = make_sample(g, 0, sh->nsrc, src_adj, adj_smp);
         HIPCHK(launch_sample(sm, LA, g->st, s));

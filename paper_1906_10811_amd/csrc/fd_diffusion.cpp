@@ -1,0 +1,102 @@
+// fd_diffusion.cpp -- the thesis's benchmark problem (Section 5.1.2): 2D
+// diffusion, first order in time, on the pitched 2D layout of libfd.  A
+// host time loop enqueues one tiled step kernel per time step, ping-ponging
+// between two workspace fields (the new level cannot overwrite the old one:
+// every point of u^n is read by its neighbours' updates).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/fd.h"
+#include "fd_api_internal.h"
+#include "fd_internal.h"
+
+using namespace fd;
+
+namespace {
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool to_grid_desc(const fd_diffusion_desc *d, fd_grid_desc *g) {
+    if (!d) return fdi_fail(FD_ERR_ARG, "null descriptor"), false;
+    if (!(d->nu > 0.0) || !std::isfinite(d->nu)) return fdi_fail(FD_ERR_ARG, "nu must be > 0"), false;
+    memset(g, 0, sizeof *g);
+    g->ndim = 2;
+    g->shape[0] = d->shape[0];
+    g->shape[1] = d->shape[1];
+    g->spacing[0] = d->spacing[0];
+    g->spacing[1] = d->spacing[1];
+    g->space_order = d->space_order;
+    g->storage = FD_STORE_F32;
+    return fdi_check_desc(g);
+}
+
+// c_j of the maximal-order central second derivative, radius r.
+void weights(int r, double *c) {
+    auto fact = [](int n) {
+        double f = 1.0;
+        for (int i = 2; i <= n; ++i) f *= i;
+        return f;
+    };
+    double sum = 0.0;
+    for (int j = 1; j <= r; ++j) {
+        c[j] = 2.0 * ((j % 2) ? 1.0 : -1.0) * fact(r) * fact(r) / ((double)j * j * fact(r - j) * fact(r + j));
+        sum += c[j];
+    }
+    c[0] = -2.0 * sum;
+}
+
+}  // namespace
+
+extern "C" int fd_diffusion_workspace_bytes(const fd_diffusion_desc *desc, size_t *bytes) {
+    fd_grid_desc g;
+    if (!bytes) return fdi_fail(FD_ERR_ARG, "null output");
+    if (!to_grid_desc(desc, &g)) return FD_ERR_ARG;
+    const Layout L = fdi_layout(&g);
+    *bytes = 2 * align_up(sizeof(float) * (size_t)L.elems, 256);
+    return FD_OK;
+}
+
+extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, size_t ws_bytes,
+                                const float *u0, float *u_out, int nt, double dt, void *stream) {
+    fd_grid_desc g;
+    if (!to_grid_desc(desc, &g)) return FD_ERR_ARG;
+    if (!workspace || !u0 || !u_out) return fdi_fail(FD_ERR_ARG, "null pointer argument");
+    if ((uintptr_t)workspace % 256) return fdi_fail(FD_ERR_ARG, "workspace must be 256-byte aligned");
+    if (nt < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fdi_fail(FD_ERR_ARG, "nt >= 0 and dt > 0");
+    const Layout L = fdi_layout(&g);
+    const size_t fb = align_up(sizeof(float) * (size_t)L.elems, 256);
+    if (ws_bytes < 2 * fb) return fdi_fail(FD_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, 2 * fb);
+    double c[kMaxR + 1];
+    weights(L.r, c);
+    double s_odd = 0.0;
+    for (int j = 1; j <= L.r; j += 2) s_odd += c[j];
+    const double hx2 = desc->spacing[0] * desc->spacing[0], hy2 = desc->spacing[1] * desc->spacing[1];
+    const double limit = 1.0 / (2.0 * s_odd * (1.0 / hx2 + 1.0 / hy2));
+    if (desc->nu * dt > limit)
+        return fdi_fail(FD_ERR_UNSTABLE, "nu dt %.6g exceeds the explicit limit %.6g", desc->nu * dt, limit);
+    hipStream_t s = (hipStream_t)stream;
+    float *A = (float *)workspace, *B = (float *)((char *)workspace + fb);
+    const double k = desc->nu * dt;
+    float wx[kMaxR + 1], wz[kMaxR + 1];
+    for (int j = 0; j <= kMaxR; ++j) {
+        wx[j] = (j >= 1 && j <= L.r) ? (float)(k * c[j] / hx2) : 0.f;
+        wz[j] = (j >= 1 && j <= L.r) ? (float)(k * c[j] / hy2) : 0.f;
+    }
+    const float w0 = (float)(k * (c[0] / hx2 + c[0] / hy2));
+    hipError_t e;
+    if ((e = launch_zero_field(L, A, Store::F32, s)) != hipSuccess ||
+        (e = launch_zero_field(L, B, Store::F32, s)) != hipSuccess ||
+        (e = launch_dense_to_field(L, u0, A, Store::F32, 1.f, s)) != hipSuccess)
+        return fdi_fail(FD_ERR_DEVICE, "diffusion setup: %s", hipGetErrorString(e));
+    for (int n = 0; n < nt; ++n) {
+        if ((e = launch_diffuse2d(L, A, B, w0, wx, wz, s)) != hipSuccess)
+            return fdi_fail(FD_ERR_DEVICE, "diffusion step: %s", hipGetErrorString(e));
+        std::swap(A, B);
+    }
+    if ((e = launch_field_to_dense(L, A, u_out, Store::F32, 1.f, s)) != hipSuccess)
+        return fdi_fail(FD_ERR_DEVICE, "diffusion readback: %s", hipGetErrorString(e));
+    return FD_OK;
+}

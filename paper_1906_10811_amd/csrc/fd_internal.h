@@ -58,15 +58,19 @@ struct Sample {
     float scale;
 };
 
-// Imaging condition fused into an adjoint step: for the new adjoint value
-// lam at a point, grad -= lam * ((u1 - 2 u0 + um) + s (u1 - um)), where s is
-// the point's sigma dt / 2.
+// Gradient support (float32 storage).  A recompute step (kBracket) also
+// writes, for time n, the imaging bracket
+//   br^n = (u^{n+1} - 2 u^n + u^{n-1}) + s (u^{n+1} - u^{n-1}),  s = sigma dt/2,
+// from the three levels it holds in registers; an adjoint step (kImage)
+// then accumulates grad -= lam^n * br^n in float64 for its new value lam^n.
+// br and grad use the pitched field layout (grad in doubles).
 struct Imaging {
-    const void *u1;         // u^{n+1}
-    const void *u0;         // u^n
-    const void *um;         // u^{n-1}
-    double *grad;           // dense padded [nz][ny][nx]
+    float *br_out;          // kBracket: bracket of the step's time level
+    const float *br_in;     // kImage: bracket of the step's time level
+    double *grad;           // kImage: float64 accumulator
 };
+
+enum StepMode { kPlain = 0, kBracket = 1, kImage = 2 };
 
 struct StepArgs {
     Layout L;
@@ -90,10 +94,10 @@ struct StepArgs {
 enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
 
 // Resident workgroups per CU of a step kernel (0 if unknown).
-int step_blocks_per_cu(int ndim, int r, Store st, bool imaging);
+int step_blocks_per_cu(int ndim, int r, Store st, int mode);
 
 // Launchers (fd_kernels.hip).  Each returns the hipError_t of the launch.
-hipError_t launch_step(const StepArgs &a, Store st, bool imaging, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s);
 hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s);
 hipError_t launch_fill_velocity(const Layout &L, const float *vp, int vp_padded, int nbl,
                                 const int *phys, float *vel, hipStream_t s);
@@ -104,8 +108,13 @@ hipError_t launch_dense_to_field(const Layout &L, const float *dense, void *f, S
                                  float scale, hipStream_t s);
 hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, Store st,
                                  float scale, hipStream_t s);
+// One explicit diffusion step, 2D: out = u + w0 u + sum_j wx_j (..) + wz_j (..)
+// (weights already multiplied by nu dt).
+hipError_t launch_diffuse2d(const Layout &L, const float *u, float *out, float w0, const float *wx,
+                            const float *wz, hipStream_t s);
 hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
                          float *resid, double *partials, int npart, double *out, hipStream_t s);
 hipError_t launch_zero_f64(double *p, long long n, hipStream_t s);
+hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, double *dense, hipStream_t s);
 
 }  // namespace fd

@@ -152,8 +152,52 @@ __device__ inline float update_point(float c, float m, float p, float lap, float
     return alpha * (2.f * c - beta * m + p * (lap + src));
 }
 
+// grad -= lam * br for the lane's 4 points (float64 accumulator; measured
+// fastest with plain loads and stores issued after the update).
+__device__ inline void image_accumulate(double *g, int nvalid, const float un[4], const float4 &br) {
+    if (nvalid >= 4) {
+        double2 g0 = *reinterpret_cast<const double2 *>(g);
+        double2 g1 = *reinterpret_cast<const double2 *>(g + 2);
+        g0.x -= (double)un[0] * (double)br.x;
+        g0.y -= (double)un[1] * (double)br.y;
+        g1.x -= (double)un[2] * (double)br.z;
+        g1.y -= (double)un[3] * (double)br.w;
+        *reinterpret_cast<double2 *>(g) = g0;
+        *reinterpret_cast<double2 *>(g + 2) = g1;
+    } else {
+        const float b[3] = {br.x, br.y, br.z};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (i < nvalid) g[i] -= (double)un[i] * (double)b[i];
+    }
+}
+
+// Gradient epilogues of a step (float32 fields, pitched offset `off` of the
+// first of 4 points, nvalid of them inside the grid).
+template <int MODE>
+__device__ inline void grad_epilogue(const Imaging &img, long long off, int nvalid, const float un[4],
+                                     const float4 &c, const float4 &m, const float s[4]) {
+    if constexpr (MODE == kBracket) {
+        float b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float u1 = un[i], u0 = comp(c, i), um = comp(m, i);
+            b[i] = (u1 - 2.f * u0 + um) + s[i] * (u1 - um);
+        }
+        if (nvalid >= 4) {
+            st4nt_f32(img.br_out + off, make_float4(b[0], b[1], b[2], b[3]));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (i < nvalid) img.br_out[off + i] = b[i];
+        }
+    } else if constexpr (MODE == kImage) {
+        image_accumulate(img.grad + off, nvalid, un, ld4nt_f32(img.br_in + off));
+    }
+}
+
 // ------------------------------------------------------------------ 3D step
-template <int R, Store S, bool IMG>
+template <int R, Store S, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     using E = Elem<S>;
     using T = typename E::T;
@@ -341,19 +385,13 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
                 for (int i = 0; i < 3; ++i)
                     if (i < nvalid) E::st(O + off + i, un[i]);
             }
-            if constexpr (IMG) {
-                const float4 f1 = E::ld4((const T *)a.img.u1 + off);
-                const float4 f0 = E::ld4((const T *)a.img.u0 + off);
-                const float4 fm = E::ld4((const T *)a.img.um + off);
-                double *g = a.img.grad + ((long long)z * L.ny + y) * L.nx + x;
+            if constexpr (MODE == kBracket) {
+                float sv[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (i < nvalid) {
-                        const float u1 = comp(f1, i), u0 = comp(f0, i), um = comp(fm, i);
-                        const float br = (u1 - 2.f * u0 + um) + (sxy[i] + sz) * (u1 - um);
-                        g[i] -= (double)un[i] * (double)br;
-                    }
-                }
+                for (int i = 0; i < 4; ++i) sv[i] = sxy[i] + sz;
+                grad_epilogue<MODE>(a.img, off, nvalid, un, q[R], cur.mv, sv);
+            } else if constexpr (MODE == kImage) {
+                image_accumulate(a.img.grad + off, nvalid, un, ld4nt_f32(a.img.br_in + off));
             }
         }
 #pragma unroll
@@ -376,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
 // ------------------------------------------------------------------ 2D step
 // Grid axes (x, z); tile 64 x 64 staged whole in LDS with an r halo; each
 // lane computes 4 x points in each of 4 rows.
-template <int R, Store S, bool IMG>
+template <int R, Store S, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
     using E = Elem<S>;
     using T = typename E::T;
@@ -468,22 +506,100 @@ __global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
             for (int i = 0; i < 3; ++i)
                 if (i < nvalid) E::st(O + off + i, un[i]);
         }
-        if constexpr (IMG) {
-            const float4 f1 = E::ld4((const T *)a.img.u1 + off);
-            const float4 f0 = E::ld4((const T *)a.img.u0 + off);
-            const float4 fm = E::ld4((const T *)a.img.um + off);
-            double *g = a.img.grad + (long long)z * L.nx + x;
+        if constexpr (MODE != kPlain) {
+            float sv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (i < nvalid) {
-                    const float u1 = comp(f1, i), u0 = comp(f0, i), um = comp(fm, i);
-                    const float br = (u1 - 2.f * u0 + um) + (sx[i] + sz) * (u1 - um);
-                    g[i] -= (double)un[i] * (double)br;
-                }
-            }
+            for (int i = 0; i < 4; ++i) sv[i] = sx[i] + sz;
+            grad_epilogue<MODE>(a.img, off, nvalid, un, cc, mc, sv);
         }
     }
 }
+
+// ------------------------------------------------------- 2D diffusion step
+// The thesis's benchmark operator: one forward-Euler step of u_t = nu Lap u.
+// Tile 64 x 64 staged in LDS with an r halo; each lane updates 4 x points in
+// each of 4 rows.  Weights carry nu dt (hoisted on the host, no division).
+struct DiffArgs {
+    Layout L;
+    const float *u;
+    float *out;
+    float w0;
+    float wx[kMaxR + 1];
+    float wz[kMaxR + 1];
+    int ntx, ntz;
+};
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_diffuse2d(const DiffArgs a) {
+    constexpr int HX4 = (R + 3) / 4;
+    constexpr int W4 = 16 + 2 * HX4;
+    constexpr int LH = kTile2Z + 2 * R;
+    __shared__ float4 lds[LH * W4];
+    const Layout L = a.L;
+    const int t = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int bx = t % a.ntx, bz = t / a.ntx;
+    const int x0 = bx * kTileX, z0 = bz * kTile2Z;
+    const int lane = (int)threadIdx.x;
+    const long long zcol = L.offset((L.nx + 3) & ~3, 0, 0);
+    for (int i = lane; i < LH * W4; i += kBlock) {
+        const int lr = i / W4, c = i - lr * W4;
+        const int gz = z0 - R + lr, gx = x0 - 4 * HX4 + 4 * c;
+        const bool ok = gz >= 0 && gz < L.nz && gx >= 0 && gx < L.nx;
+        lds[i] = *reinterpret_cast<const float4 *>(a.u + (ok ? L.offset(gx, 0, gz) : zcol));
+    }
+    __syncthreads();
+    const int tx = lane & 15, tz = lane >> 4;
+    const int x = x0 + 4 * tx;
+    if (x >= L.nx) return;
+    const int nvalid = L.nx - x;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int z = z0 + tz * 4 + rr;
+        if (z >= L.nz) break;
+        const float4 *row = lds + (R + tz * 4 + rr) * W4 + HX4 + tx;
+        float xs[4 * (2 * HX4 + 1)];
+#pragma unroll
+        for (int c = -HX4; c <= HX4; ++c) {
+            const float4 v = row[c];
+            xs[4 * (c + HX4) + 0] = v.x;
+            xs[4 * (c + HX4) + 1] = v.y;
+            xs[4 * (c + HX4) + 2] = v.z;
+            xs[4 * (c + HX4) + 3] = v.w;
+        }
+        float un[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) un[i] = a.w0 * xs[4 * HX4 + i];
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const float4 zp = row[j * W4], zm = row[-j * W4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float acc = a.wx[j] * (xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j]);
+                acc += a.wz[j] * (comp(zp, i) + comp(zm, i));
+                un[i] += acc;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) un[i] += xs[4 * HX4 + i];
+        const long long off = L.offset(x, 0, z);
+        if (nvalid >= 4) {
+            st4nt_f32(a.out + off, make_float4(un[0], un[1], un[2], un[3]));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (i < nvalid) a.out[off + i] = un[i];
+        }
+    }
+}
+
+template <int... Rs>
+struct DiffTable {
+    static void (*get(int r))(const DiffArgs) {
+        void (*f)(const DiffArgs) = nullptr;
+        ((r == Rs ? (f = k_diffuse2d<Rs>, 0) : 0), ...);
+        return f;
+    }
+};
 
 template <Store S>
 __global__ void k_sample(const Sample s, const void *field) {
@@ -615,24 +731,36 @@ __global__ void k_misfit_final(const double *partials, int npart, double *out) {
 // ------------------------------------------------------------ dispatch tables
 using StepFn = void (*)(const StepArgs);
 
-template <Store S, bool IMG, int... Rs>
+template <Store S, int MODE, int... Rs>
 struct Table {
     static StepFn get3(int r) {
         StepFn f = nullptr;
-        ((r == Rs ? (f = k_step3d<Rs, S, IMG>, 0) : 0), ...);
+        ((r == Rs ? (f = k_step3d<Rs, S, MODE>, 0) : 0), ...);
         return f;
     }
     static StepFn get2(int r) {
         StepFn f = nullptr;
-        ((r == Rs ? (f = k_step2d<Rs, S, IMG>, 0) : 0), ...);
+        ((r == Rs ? (f = k_step2d<Rs, S, MODE>, 0) : 0), ...);
         return f;
     }
 };
 
-template <Store S, bool IMG>
+template <Store S, int MODE>
 StepFn pick(int ndim, int r) {
-    using Tb = Table<S, IMG, 1, 2, 3, 4, 5, 6, 7, 8>;
+    using Tb = Table<S, MODE, 1, 2, 3, 4, 5, 6, 7, 8>;
     return ndim == 3 ? Tb::get3(r) : Tb::get2(r);
+}
+
+// The gradient modes exist for float32 storage only.
+StepFn pick_step(int ndim, int r, Store st, int mode) {
+    if (mode == kBracket) return st == Store::F32 ? pick<Store::F32, kBracket>(ndim, r) : nullptr;
+    if (mode == kImage) return st == Store::F32 ? pick<Store::F32, kImage>(ndim, r) : nullptr;
+    switch (st) {
+        case Store::F32: return pick<Store::F32, kPlain>(ndim, r);
+        case Store::F16: return pick<Store::F16, kPlain>(ndim, r);
+        case Store::BF16: return pick<Store::BF16, kPlain>(ndim, r);
+    }
+    return nullptr;
 }
 
 inline int grid_for(long long n) {
@@ -644,19 +772,8 @@ inline int grid_for(long long n) {
 
 }  // namespace
 
-hipError_t launch_step(const StepArgs &a, Store st, bool imaging, hipStream_t s) {
-    StepFn f = nullptr;
-    const int r = a.L.r;
-    if (imaging) {
-        if (st != Store::F32) return hipErrorInvalidValue;   // the gradient runs in float32
-        f = pick<Store::F32, true>(a.L.ndim, r);
-    } else {
-        switch (st) {
-            case Store::F32: f = pick<Store::F32, false>(a.L.ndim, r); break;
-            case Store::F16: f = pick<Store::F16, false>(a.L.ndim, r); break;
-            case Store::BF16: f = pick<Store::BF16, false>(a.L.ndim, r); break;
-        }
-    }
+hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s) {
+    StepFn f = pick_step(a.L.ndim, a.L.r, st, mode);
     if (!f) return hipErrorInvalidValue;
     const int tiles = a.ntx * a.nty * a.ntz;
     const int blocks = tiles + a.nsamp_blocks;
@@ -665,18 +782,8 @@ hipError_t launch_step(const StepArgs &a, Store st, bool imaging, hipStream_t s)
     return hipGetLastError();
 }
 
-int step_blocks_per_cu(int ndim, int r, Store st, bool imaging) {
-    StepFn f = nullptr;
-    if (imaging) {
-        if (st != Store::F32) return 0;
-        f = pick<Store::F32, true>(ndim, r);
-    } else {
-        switch (st) {
-            case Store::F32: f = pick<Store::F32, false>(ndim, r); break;
-            case Store::F16: f = pick<Store::F16, false>(ndim, r); break;
-            case Store::BF16: f = pick<Store::BF16, false>(ndim, r); break;
-        }
-    }
+int step_blocks_per_cu(int ndim, int r, Store st, int mode) {
+    StepFn f = pick_step(ndim, r, st, mode);
     if (!f) return 0;
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(f), kBlock, 0) !=
@@ -750,6 +857,44 @@ hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, S
         case Store::F16: hipLaunchKernelGGL(k_field_to_dense<Store::F16>, g, b, 0, s, L, f, dense, scale); break;
         case Store::BF16: hipLaunchKernelGGL(k_field_to_dense<Store::BF16>, g, b, 0, s, L, f, dense, scale); break;
     }
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void k_field_to_dense_f64(const Layout L, const double *f, double *dense) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        dense[i] = f[L.offset(x, y, z)];
+    }
+}
+}  // namespace
+
+hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, double *dense, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_field_to_dense_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, L, f, dense);
+    return hipGetLastError();
+}
+
+hipError_t launch_diffuse2d(const Layout &L, const float *u, float *out, float w0, const float *wx,
+                            const float *wz, hipStream_t s) {
+    auto f = DiffTable<1, 2, 3, 4, 5, 6, 7, 8>::get(L.r);
+    if (!f || L.ndim != 2) return hipErrorInvalidValue;
+    DiffArgs a{};
+    a.L = L;
+    a.u = u;
+    a.out = out;
+    a.w0 = w0;
+    for (int j = 0; j <= kMaxR; ++j) {
+        a.wx[j] = wx[j];
+        a.wz[j] = wz[j];
+    }
+    a.ntx = (L.nx + kTileX - 1) / kTileX;
+    a.ntz = (L.nz + kTile2Z - 1) / kTile2Z;
+    hipLaunchKernelGGL(f, dim3(a.ntx * a.ntz), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -481,3 +481,67 @@ def test_gradient_matches_finite_differences():
     fd = (J(m0 + eps * dm_layer) - J(m0 - eps * dm_layer)) / (2 * eps)
     an = float(np.sum(grad * dm_layer))
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+# ---------------------------------------------------- 2D diffusion (Sec 5.1.2)
+def _printed_so2_kernel(u, dt, hx, hy, hoisted):
+    """The so-2 diffusion kernel as printed (Section 3.2.2 with divisions;
+    Section 5.1.5 with hoisted reciprocals), evaluated on interior points of
+    a zero-padded copy; axis 0 of the array is y, axis 1 is x."""
+    up = np.pad(u, 1)
+    c = up[1:-1, 1:-1]
+    xm, xp = up[1:-1, :-2], up[1:-1, 2:]
+    ym, yp = up[:-2, 1:-1], up[2:, 1:-1]
+    if hoisted:
+        r0 = 1.0 / (hy * hy)
+        r1 = 1.0 / (hx * hx)
+        return (-1.0 * (dt * c * r1 + dt * c * r0)
+                + 0.5 * (dt * xm * r1 + dt * xp * r1 + dt * ym * r0 + dt * yp * r0) + c)
+    return (-1.0 * (dt * c / (hy * hy) + dt * c / (hx * hx))
+            + 0.5 * (dt * ym / (hy * hy) + dt * xm / (hx * hx) + dt * yp / (hy * hy) + dt * xp / (hx * hx)) + c)
+
+
+@pytest.mark.parametrize("hoisted", [False, True])
+def test_diffusion_step_matches_printed_kernel(hoisted):
+    """One oracle diffusion step at so 2, nu = 0.5 equals the printed OPS
+    kernel (both listings agree to rounding)."""
+    g = oracle.Grid((23, 17), (0.7, 1.3), (0.0, 0.0), 2)
+    rng = np.random.default_rng(8)
+    u0 = rng.standard_normal(g.array_shape)
+    dt = 0.1
+    got = oracle.diffusion(g, u0, 0.5, dt, 1)
+    want = _printed_so2_kernel(u0, dt, 0.7, 1.3, hoisted)
+    assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 12])
+def test_diffusion_fourier_mode_decay(so):
+    """Away from the faces a Fourier mode decays by exactly
+    g = 1 - nu dt sum_a h_a^-2 (-c_0 - 2 sum_j c_j cos(j k_a h_a)) per step."""
+    n = 6
+    r = so // 2
+    g = oracle.Grid((2 * n * r + 30, 2 * n * r + 26), (1.0, 1.5), (0.0, 0.0), so)
+    nu = 0.5
+    dt = 0.8 * oracle.diffusion_critical_dt(g, nu)
+    k = (0.41, 0.37)
+    c = oracle.fd_weights(so)
+    lam = sum((-c[0] - 2.0 * sum(c[j] * math.cos(j * k[a] * g.spacing[a]) for j in range(1, r + 1)))
+              / g.spacing[a] ** 2 for a in range(2))
+    fac = 1.0 - nu * dt * lam
+    Z, X = np.meshgrid(np.arange(g.padded[1]) * g.spacing[1], np.arange(g.padded[0]) * g.spacing[0], indexing="ij")
+    u0 = np.cos(k[0] * X + 0.2) * np.cos(k[1] * Z - 0.3)
+    u = oracle.diffusion(g, u0, nu, dt, n)
+    m = n * r
+    assert np.max(np.abs(u[m:-m, m:-m] - fac ** n * u0[m:-m, m:-m])) <= 1e-12
+    assert abs(fac) < 1.0
+
+
+def test_diffusion_stability_limit():
+    g = oracle.Grid((48, 48), (1.0, 1.0), (0.0, 0.0), 8)
+    rng = np.random.default_rng(1)
+    u0 = rng.standard_normal(g.array_shape)
+    lim = oracle.diffusion_critical_dt(g, 0.5)
+    ok = oracle.diffusion(g, u0, 0.5, 0.98 * lim, 400)
+    bad = oracle.diffusion(g, u0, 0.5, 1.05 * lim, 400)
+    assert np.max(np.abs(ok)) <= np.max(np.abs(u0))
+    assert np.max(np.abs(bad)) > 1e3 * np.max(np.abs(u0))
