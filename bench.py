@@ -271,18 +271,32 @@ def bench_diffusion(torch, dev, stream):
                 c[j] = 2 * (-1) ** (j + 1) * math.factorial(r) ** 2 / (j * j * math.factorial(r - j) * math.factorial(r + j))
             s_odd = sum(c[j] for j in range(1, r + 1, 2))
             dt = 0.8 / (2.0 * s_odd * 2.0 / h ** 2) / 0.5
-            diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream)
+            diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream, time_block=1)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             with torch.cuda.stream(stream):
                 e0.record(stream)
-                diffusion(u0, (h, h), so, 0.5, dt, 1000, out=res, stream=stream)
+                diffusion(u0, (h, h), so, 0.5, dt, 1000, out=res, stream=stream, time_block=1)
                 e1.record(stream)
             torch.cuda.synchronize()
             secs = e0.elapsed_time(e1) / 1000.0
             gpts = n * n * 1000 / secs / 1e9
-            out["%d^2 so%d" % (n, so)] = dict(gpts=round(gpts, 1), frac_hbm=round(gpts * 8.0 / HBM_PEAK_GBS, 4))
+            # temporally blocked: 16/r steps per launch, 8 B per point per launch
+            lev = 16 // r
+            diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream, time_block=lev)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                e0.record(stream)
+                diffusion(u0, (h, h), so, 0.5, dt, 1000, out=res, stream=stream, time_block=lev)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            secs_tb = e0.elapsed_time(e1) / 1000.0
+            gpts_tb = n * n * 1000 / secs_tb / 1e9
+            out["%d^2 so%d" % (n, so)] = dict(
+                gpts=round(gpts, 1), frac_hbm=round(gpts * 8.0 / HBM_PEAK_GBS, 4),
+                blocked_gpts=round(gpts_tb, 1), steps_per_launch=lev,
+                blocked_frac_hbm=round(gpts_tb * 8.0 / lev / HBM_PEAK_GBS, 4))
         del u0, res
     return out
 

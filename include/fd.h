@@ -161,15 +161,47 @@ int fd_adjoint(fd_grid *grid, const fd_shot *shot, int nt, double dt,
 
 /* Flags for fd_gradient. */
 #define FD_GRAD_RESIDUAL_GIVEN 1   /* d_obs_dev holds the residual itself */
+#define FD_GRAD_BINOMIAL 2         /* checkpoint_every is a number of snapshot slots (>= 0);
+                                      the reverse sweep follows fd_checkpoint_schedule */
 
-/* Device workspace for fd_gradient: checkpoints of (u^c, u^{c-1}) every
- * checkpoint_every steps, a recompute buffer of checkpoint_every+2 fields,
- * and the traces and residual. */
+/* Device workspace for fd_gradient.  Default: checkpoints of (u^c, u^{c-1})
+ * every checkpoint_every steps and checkpoint_every bracket fields of the
+ * segment recompute.  FD_GRAD_BINOMIAL: checkpoint_every + 1 snapshots and
+ * two scratch fields.  Both add the float64 accumulator, traces and
+ * residual. */
 int fd_gradient_workspace_bytes(const fd_grid *grid, int nt, int nrec,
-                                int checkpoint_every, size_t *bytes);
+                                int checkpoint_every, int flags, size_t *bytes);
+
+/* Actions of a binomial checkpoint schedule (host only, no device work). */
+typedef enum fd_ckpt_kind {
+    FD_ACT_ADVANCE = 1,   /* `count` forward steps from level `step` */
+    FD_ACT_STORE = 2,     /* snapshot of the state at level `step` into `slot` */
+    FD_ACT_RESTORE = 3,   /* make the state of `slot` (level `step`) current */
+    FD_ACT_YOUTURN = 4    /* forward step `step` with its imaging bracket, then the
+                             adjoint step producing lambda^step */
+} fd_ckpt_kind;
+
+typedef struct fd_ckpt_action {
+    int kind;     /* fd_ckpt_kind */
+    int step;     /* time level the action starts from */
+    int count;    /* steps (ADVANCE), 1 (YOUTURN), 0 otherwise */
+    int slot;     /* snapshot slot (STORE, RESTORE; 0 holds the initial state) */
+    int first;    /* 1 if the action computes some step for the first time */
+} fd_ckpt_action;
 
 /*
- * Misfit and gradient with respect to m = 1/v^2 on the padded grid:
+ * Schedule reversing nt steps with `slots` snapshot slots besides the initial
+ * state, minimising the number of forward steps (binomial checkpointing,
+ * Griewank-Walther; split points found by dynamic programming).  Writes up
+ * to `capacity` actions (actions may be NULL to query the count), the count
+ * to *n_actions and the ADVANCE steps to *forward_steps (nullable).
+ */
+int fd_checkpoint_schedule(int nt, int slots, fd_ckpt_action *actions, int capacity,
+                           int *n_actions, long long *forward_steps);
+
+/*
+ * Misfit and gradient with respect to m = 1/v^2 on the padded grid (both
+ * checkpointing modes give bitwise the same result):
  *   J = 1/2 sum_n sum_r (rec_r[n] - d_obs_r[n])^2
  *   g_m = - sum_n lambda^n [(u^{n+1} - 2u^n + u^{n-1}) + (sigma dt/2)(u^{n+1} - u^{n-1})]
  * with lambda the adjoint field driven by the residual.  Forward wavefields
@@ -247,6 +279,8 @@ typedef struct fd_diffusion_desc {
     double spacing[2];     /* h_x, h_y > 0 */
     int space_order;       /* even, 2..16 */
     double nu;             /* diffusivity > 0 */
+    int time_block;        /* steps per launch: 0 = as many as the tile halo allows
+                              (16 / (so/2)), 1 = one step per launch, k = at most k */
 } fd_diffusion_desc;
 
 /* Device workspace for fd_diffusion_run (two pitched float32 fields). */

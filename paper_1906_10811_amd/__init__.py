@@ -172,9 +172,11 @@ class Grid:
 
     def gradient(self, src_xyz, wavelet: torch.Tensor, rec_xyz, d_obs: torch.Tensor, dt: float,
                  checkpoint_every: int = 50, residual_given: bool = False, want_src_adj: bool = False,
-                 stream=None):
+                 binomial_slots: int | None = None, stream=None):
         """fd_gradient.  Returns (misfit [1] float64, g_m dense padded float64,
-        traces [nt, nrec], F^T residual [nt, nsrc] or None)."""
+        traces [nt, nrec], F^T residual [nt, nsrc] or None).  binomial_slots
+        > 0 selects the binomial checkpoint schedule with that many snapshot
+        slots (0 allowed) instead of checkpoints every checkpoint_every steps."""
         lib = _lib.load()
         wav = _dev_f32(wavelet, "wavelet")
         if wav.dim() == 1:
@@ -182,18 +184,21 @@ class Grid:
         obs = _dev_f32(d_obs, "d_obs")
         nt = obs.shape[0]
         sh, keep = self._shot(src_xyz, wav, rec_xyz)
+        flags = _lib.FD_GRAD_RESIDUAL_GIVEN if residual_given else 0
+        K = int(checkpoint_every)
+        if binomial_slots is not None:
+            flags |= _lib.FD_GRAD_BINOMIAL
+            K = int(binomial_slots)
         nbytes = ctypes.c_size_t()
-        _lib.check(lib.fd_gradient_workspace_bytes(self._h, nt, sh.nrec, int(checkpoint_every),
-                                                   ctypes.byref(nbytes)))
+        _lib.check(lib.fd_gradient_workspace_bytes(self._h, nt, sh.nrec, K, flags, ctypes.byref(nbytes)))
         ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
         aligned = (ws.data_ptr() + 255) // 256 * 256
         misfit = torch.empty(1, dtype=torch.float64, device=self.device)
         grad = torch.empty(self.array_shape, dtype=torch.float64, device=self.device)
         rec = torch.empty((nt, sh.nrec), dtype=torch.float32, device=self.device)
         sadj = torch.empty((nt, sh.nsrc), dtype=torch.float32, device=self.device) if want_src_adj else None
-        flags = _lib.FD_GRAD_RESIDUAL_GIVEN if residual_given else 0
         _lib.check(lib.fd_gradient(self._h, ctypes.byref(sh), nt, float(dt), ctypes.c_void_p(obs.data_ptr()),
-                                   int(checkpoint_every), flags, ctypes.c_void_p(aligned), nbytes.value,
+                                   K, flags, ctypes.c_void_p(aligned), nbytes.value,
                                    ctypes.c_void_p(misfit.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
                                    ctypes.c_void_p(rec.data_ptr()),
                                    ctypes.c_void_p(sadj.data_ptr()) if sadj is not None else None,
@@ -332,9 +337,10 @@ class Server:
 
 
 def diffusion(u0: torch.Tensor, spacing, space_order: int, nu: float, dt: float, nt: int,
-              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+              out: torch.Tensor | None = None, time_block: int = 0, stream=None) -> torch.Tensor:
     """fd_diffusion_run: nt explicit steps of u_t = nu (u_xx + u_yy) from the
-    CUDA float32 field u0 [Ny, Nx]; returns u^nt (a new tensor unless `out`)."""
+    CUDA float32 field u0 [Ny, Nx]; returns u^nt (a new tensor unless `out`).
+    time_block: steps per launch (0: as many as the tile halo allows)."""
     lib = _lib.load()
     u = _dev_f32(u0, "u0")
     if u.dim() != 2:
@@ -344,6 +350,7 @@ def diffusion(u0: torch.Tensor, spacing, space_order: int, nu: float, dt: float,
     d.spacing[0], d.spacing[1] = float(spacing[0]), float(spacing[1])
     d.space_order = int(space_order)
     d.nu = float(nu)
+    d.time_block = int(time_block)
     nbytes = ctypes.c_size_t()
     _lib.check(lib.fd_diffusion_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
     ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=u.device)

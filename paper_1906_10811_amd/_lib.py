@@ -23,6 +23,9 @@ FD_STORE_F16 = 1
 FD_STORE_BF16 = 2
 
 FD_GRAD_RESIDUAL_GIVEN = 1
+FD_GRAD_BINOMIAL = 2
+
+FD_ACT_ADVANCE, FD_ACT_STORE, FD_ACT_RESTORE, FD_ACT_YOUTURN = 1, 2, 3, 4
 
 # every symbol include/fd.h declares
 EXPORTS = (
@@ -30,6 +33,7 @@ EXPORTS = (
     "fd_forward", "fd_adjoint", "fd_gradient_workspace_bytes", "fd_gradient",
     "fd_server_create", "fd_submit", "fd_wait", "fd_request_bytes", "fd_server_stats",
     "fd_server_destroy", "fd_last_error", "fd_diffusion_workspace_bytes", "fd_diffusion_run",
+    "fd_checkpoint_schedule",
 )
 
 
@@ -122,6 +126,17 @@ class DiffusionDesc(ctypes.Structure):
         ("spacing", ctypes.c_double * 2),
         ("space_order", ctypes.c_int),
         ("nu", ctypes.c_double),
+        ("time_block", ctypes.c_int),
+    ]
+
+
+class CkptAction(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("step", ctypes.c_int),
+        ("count", ctypes.c_int),
+        ("slot", ctypes.c_int),
+        ("first", ctypes.c_int),
     ]
 
 
@@ -152,7 +167,7 @@ def load() -> ctypes.CDLL:
         "fd_grid_get_info": (I, [P, ctypes.POINTER(GridInfo)]),
         "fd_forward": (I, [P, ctypes.POINTER(Shot), I, D, P, ctypes.POINTER(FwdOpts), P]),
         "fd_adjoint": (I, [P, ctypes.POINTER(Shot), I, D, P, P, P]),
-        "fd_gradient_workspace_bytes": (I, [P, I, I, I, PS]),
+        "fd_gradient_workspace_bytes": (I, [P, I, I, I, I, PS]),
         "fd_gradient": (I, [P, ctypes.POINTER(Shot), I, D, P, I, I, P, S, P, P, P, P, P]),
         "fd_server_create": (I, [ctypes.POINTER(ServerDesc), ctypes.POINTER(P)]),
         "fd_submit": (I, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -163,6 +178,8 @@ def load() -> ctypes.CDLL:
         "fd_last_error": (ctypes.c_char_p, []),
         "fd_diffusion_workspace_bytes": (I, [ctypes.POINTER(DiffusionDesc), PS]),
         "fd_diffusion_run": (I, [ctypes.POINTER(DiffusionDesc), P, S, P, P, I, D, P]),
+        "fd_checkpoint_schedule": (I, [I, I, ctypes.POINTER(CkptAction), I, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_longlong)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -176,3 +193,15 @@ def check(rc: int) -> None:
     if rc != FD_OK:
         msg = load().fd_last_error().decode(errors="replace")
         raise FDError(rc, msg)
+
+
+def checkpoint_schedule(nt: int, slots: int):
+    """fd_checkpoint_schedule as a list of (kind, step, count, slot, first)
+    plus the number of forward steps it advances (host only)."""
+    lib = load()
+    n = ctypes.c_int()
+    fwd = ctypes.c_longlong()
+    check(lib.fd_checkpoint_schedule(int(nt), int(slots), None, 0, ctypes.byref(n), ctypes.byref(fwd)))
+    arr = (CkptAction * max(1, n.value))()
+    check(lib.fd_checkpoint_schedule(int(nt), int(slots), arr, n.value, ctypes.byref(n), ctypes.byref(fwd)))
+    return [(a.kind, a.step, a.count, a.slot, a.first) for a in arr[:n.value]], fwd.value

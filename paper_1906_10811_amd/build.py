@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libfd.so")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["fd_kernels.hip"]
-HOST_SOURCES = ["fd_api.cpp", "fd_serve.cpp", "fd_diffusion.cpp"]
+HOST_SOURCES = ["fd_api.cpp", "fd_serve.cpp", "fd_diffusion.cpp", "fd_checkpoint.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]

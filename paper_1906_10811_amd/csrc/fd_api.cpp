@@ -775,18 +775,22 @@ extern "C" int fd_adjoint(fd_grid *g, const fd_shot *sh, int nt, double dt,
 }
 
 namespace {
-// Gradient workspace: 2 checkpoint fields every K steps, the two rotating
-// fields of the segment recompute, K imaging brackets (float32 fields), the
-// float64 accumulator in the pitched layout, traces and residual.
+// Gradient workspace.  Fixed interval K: 2 checkpoint fields every K steps,
+// the two rotating fields of the segment recompute and K imaging brackets.
+// Binomial (K = number of snapshot slots): K+1 snapshot pairs, the state
+// pair, the output field of the bracket step and one bracket.  Both: the
+// float64 accumulator (pitched), traces and residual.
 struct GradPlan {
     size_t ckpt, rot, br, grad, rec, resid, total;
     int ncp, K, nbr;
+    bool binomial;
 };
-GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K) {
+GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K, int flags) {
     GradPlan p{};
     p.K = K;
-    p.ncp = (nt + K - 1) / K;
-    p.nbr = std::min(K, nt);
+    p.binomial = (flags & FD_GRAD_BINOMIAL) != 0;
+    p.ncp = p.binomial ? std::min(K, nt) + 1 : (nt + K - 1) / K;
+    p.nbr = p.binomial ? 2 : std::min(K, nt);   // binomial: output field + bracket
     const size_t fb = g->wp.field_bytes;
     size_t o = 0;
     p.ckpt = o; o += fb * 2 * (size_t)p.ncp;
@@ -800,11 +804,12 @@ GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K) {
 }
 }  // namespace
 
-extern "C" int fd_gradient_workspace_bytes(const fd_grid *g, int nt, int nrec, int K, size_t *bytes) {
+extern "C" int fd_gradient_workspace_bytes(const fd_grid *g, int nt, int nrec, int K, int flags, size_t *bytes) {
     API_GUARD_BEGIN
     if (!g || !bytes) return fdi_fail(FD_ERR_ARG, "null argument");
-    if (nt < 1 || nrec < 1 || K < 1) return fdi_fail(FD_ERR_ARG, "nt, nrec and checkpoint_every must be >= 1");
-    *bytes = grad_plan(g, nt, nrec, K).total;
+    if (nt < 1 || nrec < 1 || K < ((flags & FD_GRAD_BINOMIAL) ? 0 : 1))
+        return fdi_fail(FD_ERR_ARG, "nt, nrec >= 1; checkpoint_every >= 1 (>= 0 snapshot slots when binomial)");
+    *bytes = grad_plan(g, nt, nrec, K, flags).total;
     return FD_OK;
     API_GUARD_END
 }
@@ -817,18 +822,22 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     int rc;
     if ((rc = check_shot(g, sh))) return rc;
     if ((rc = check_dt(g, dt, nt))) return rc;
-    if (nt < 1 || K < 1) return fdi_fail(FD_ERR_ARG, "nt and checkpoint_every must be >= 1");
+    if (nt < 1 || K < ((flags & FD_GRAD_BINOMIAL) ? 0 : 1))
+        return fdi_fail(FD_ERR_ARG, "nt >= 1; checkpoint_every >= 1 (>= 0 snapshot slots when binomial)");
     if (g->st != Store::F32) return fdi_fail(FD_ERR_ARG, "fd_gradient needs float32 storage");
     if (!d_obs || !misfit || !grad_m || !workspace || !sh->src_wavelet)
         return fdi_fail(FD_ERR_ARG, "null pointer argument");
     if ((uintptr_t)workspace % 256) return fdi_fail(FD_ERR_ARG, "workspace must be 256-byte aligned");
-    const GradPlan gp = grad_plan(g, nt, sh->nrec, K);
+    const GradPlan gp = grad_plan(g, nt, sh->nrec, K, flags);
     if (ws_bytes < gp.total) return fdi_fail(FD_ERR_NOMEM, "gradient workspace %zu < %zu", ws_bytes, gp.total);
+    std::vector<fd_ckpt_action> plan;
+    if (gp.binomial && (rc = fdi_checkpoint_plan(nt, K, &plan, nullptr))) return rc;
     DeviceGuard dg(g->device);
     hipStream_t s = (hipStream_t)stream;
     if ((rc = ensure_dt(g, dt, s))) return rc;
     if ((rc = ensure_side(g, 0, sh->nsrc, sh->src_xyz, s))) return rc;
     if ((rc = ensure_side(g, 1, sh->nrec, sh->rec_xyz, s))) return rc;
+    note_stream(g, s);
     const Layout &L = g->L;
     char *ws = (char *)workspace;
     const size_t fb = g->wp.field_bytes;
@@ -840,61 +849,137 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     double *gacc = (double *)(ws + gp.grad);
     float *recb = (float *)(ws + gp.rec);
     float *resid = (float *)(ws + gp.resid);
-
-    // 1. forward with checkpoints of (u^c, u^{c-1}) every K steps
-    HIPCHK(launch_zero_field(L, g->uA, g->st, s));
-    HIPCHK(launch_zero_field(L, g->uB, g->st, s));
-    if ((rc = fdi_forward_steps(g, sh, nt, 0, nt, recb, ck.data(), K, s))) return rc;
-    // 2. residual and misfit (FP64)
     const long long nres = (long long)nt * sh->nrec;
-    HIPCHK(launch_misfit(recb, d_obs, nres, (flags & FD_GRAD_RESIDUAL_GIVEN) ? 1 : 0, resid,
-                         g->partials, kNPart, misfit, s));
-    // 3. adjoint sweep over segments, last to first.  Each segment is
-    //    recomputed from its checkpoint, writing the imaging bracket of every
-    //    time level; the adjoint steps then read one bracket per point.
-    HIPCHK(launch_zero_f64(gacc, L.elems, s));
-    HIPCHK(launch_zero_field(L, g->uA, g->st, s));
-    HIPCHK(launch_zero_field(L, g->uB, g->st, s));
-    void *LA = g->uA, *LB = g->uB;   // lambda^k, lambda^{k+1}
+    const int given = (flags & FD_GRAD_RESIDUAL_GIVEN) ? 1 : 0;
+
     StepArgs a = base_args(g);
     const float fwd_inj = (float)(1.0 / g->cell);
     const float adj_inj = (float)(1.0 / (dt * dt));
     const float adj_smp = (float)(dt * dt / g->cell);
-    for (int seg = gp.ncp - 1; seg >= 0; --seg) {
-        const int c = seg * K;
-        const int e = std::min(c + K, nt);
-        HIPCHK(hipMemcpyAsync(rotA, ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(rotB, ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
-        void *A = rotA, *B = rotB;   // u^n, u^{n-1}
-        for (int n = c; n < e; ++n) {
-            a.u = A;
-            a.prev = B;
-            a.out = B;
-            a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, fwd_inj);
-            a.smp = Sample{};
-            a.nsamp_blocks = 0;
-            a.img = Imaging{};
-            a.img.br_out = br[n - c];
-            a.ntz = g->ntz[kBracket];
-            a.zchunk = g->zchunk[kBracket];
-            HIPCHK(launch_step(a, g->st, kBracket, s));
-            std::swap(A, B);
+    void *LA = g->uA, *LB = g->uB;   // lambda^k, lambda^{k+1}
+    // forward step n with the imaging bracket of level n into `brf`
+    auto bracket_step = [&](int n, void *u, void *prev, void *out, float *brf, float *rec_row) -> int {
+        a.u = u;
+        a.prev = prev;
+        a.out = out;
+        a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, fwd_inj);
+        a.smp = make_sample(g, 1, sh->nrec, rec_row, 1.f);
+        a.nsamp_blocks = samp_blocks(a.smp);
+        a.img = Imaging{};
+        a.img.br_out = brf;
+        a.ntz = g->ntz[kBracket];
+        a.zchunk = g->zchunk[kBracket];
+        HIPCHK(launch_step(a, g->st, kBracket, s));
+        return FD_OK;
+    };
+    // adjoint step k: lambda^{k-1} from lambda^k, lambda^{k+1}, residual row
+    // k-1, and grad -= lambda^{k-1} * bracket of level k-1
+    auto adjoint_step = [&](int k, const float *brf) -> int {
+        a.u = LA;
+        a.prev = LB;
+        a.out = LB;
+        a.inj = make_inject(g, 1, resid + (size_t)(k - 1) * sh->nrec, adj_inj);
+        a.smp = make_sample(g, 0, sh->nsrc, (src_adj && k <= nt - 1) ? src_adj + (size_t)k * sh->nsrc : nullptr,
+                            adj_smp);
+        a.nsamp_blocks = samp_blocks(a.smp);
+        a.img = Imaging{};
+        a.img.br_in = brf;
+        a.img.grad = gacc;
+        a.ntz = g->ntz[kImage];
+        a.zchunk = g->zchunk[kImage];
+        HIPCHK(launch_step(a, g->st, kImage, s));
+        std::swap(LA, LB);
+        return FD_OK;
+    };
+    HIPCHK(launch_zero_f64(gacc, L.elems, s));
+
+    if (!gp.binomial) {
+        // 1. forward with checkpoints of (u^c, u^{c-1}) every K steps
+        HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+        HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+        if ((rc = fdi_forward_steps(g, sh, nt, 0, nt, recb, ck.data(), K, s))) return rc;
+        // 2. residual and misfit (FP64)
+        HIPCHK(launch_misfit(recb, d_obs, nres, given, resid, g->partials, kNPart, misfit, s));
+        // 3. adjoint sweep over segments, last to first.  Each segment is
+        //    recomputed from its checkpoint, writing the imaging bracket of
+        //    every time level; the adjoint steps read one bracket per point.
+        HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+        HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+        for (int seg = gp.ncp - 1; seg >= 0; --seg) {
+            const int c = seg * K;
+            const int e = std::min(c + K, nt);
+            HIPCHK(hipMemcpyAsync(rotA, ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(rotB, ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
+            void *A = rotA, *B = rotB;   // u^n, u^{n-1}
+            for (int n = c; n < e; ++n) {
+                if ((rc = bracket_step(n, A, B, B, br[n - c], nullptr))) return rc;
+                std::swap(A, B);
+            }
+            for (int k = e; k >= c + 1; --k)
+                if ((rc = adjoint_step(k, br[k - 1 - c]))) return rc;
         }
-        for (int k = e; k >= c + 1; --k) {
-            a.u = LA;
-            a.prev = LB;
-            a.out = LB;
-            a.inj = make_inject(g, 1, resid + (size_t)(k - 1) * sh->nrec, adj_inj);
-            a.smp = make_sample(g, 0, sh->nsrc, (src_adj && k <= nt - 1) ? src_adj + (size_t)k * sh->nsrc : nullptr,
-                                adj_smp);
-            a.nsamp_blocks = samp_blocks(a.smp);
-            a.img = Imaging{};
-            a.img.br_in = br[k - 1 - c];
-            a.img.grad = gacc;
-            a.ntz = g->ntz[kImage];
-            a.zchunk = g->zchunk[kImage];
-            HIPCHK(launch_step(a, g->st, kImage, s));
-            std::swap(LA, LB);
+    } else {
+        // Binomial schedule: the state pair (A = u^n, B = u^{n-1}) moves by
+        // ADVANCE, is saved by STORE and reset by RESTORE; YOUTURN takes one
+        // bracket step out of place and the adjoint step that consumes it.
+        // The first sweep samples the receivers; the first YOUTURN (level
+        // nt-1) completes the traces and forms the residual.
+        void *A = rotA, *B = rotB;
+        float *out_f = br[0], *brf = br[1];
+        HIPCHK(launch_zero_field(L, A, g->st, s));
+        HIPCHK(launch_zero_field(L, B, g->st, s));
+        HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+        HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+        HIPCHK(hipMemcpyAsync(ck[0], A, fb, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(ck[1], B, fb, hipMemcpyDeviceToDevice, s));
+        int cur = 0;   // level held by (A, B), -1 if it is not a stored one
+        for (const fd_ckpt_action &act : plan) {
+            switch (act.kind) {
+                case FD_ACT_STORE:
+                    HIPCHK(hipMemcpyAsync(ck[2 * act.slot], A, fb, hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(ck[2 * act.slot + 1], B, fb, hipMemcpyDeviceToDevice, s));
+                    cur = act.step;
+                    break;
+                case FD_ACT_RESTORE:
+                    if (cur != act.step) {
+                        HIPCHK(hipMemcpyAsync(A, ck[2 * act.slot], fb, hipMemcpyDeviceToDevice, s));
+                        HIPCHK(hipMemcpyAsync(B, ck[2 * act.slot + 1], fb, hipMemcpyDeviceToDevice, s));
+                        cur = act.step;
+                    }
+                    break;
+                case FD_ACT_ADVANCE:
+                    for (int n = act.step; n < act.step + act.count; ++n) {
+                        a.u = A;
+                        a.prev = B;
+                        a.out = B;
+                        a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, fwd_inj);
+                        a.smp = make_sample(g, 1, sh->nrec,
+                                            (act.first && n >= 1) ? recb + (size_t)(n - 1) * sh->nrec : nullptr, 1.f);
+                        a.nsamp_blocks = samp_blocks(a.smp);
+                        a.img = Imaging{};
+                        a.ntz = g->ntz[kPlain];
+                        a.zchunk = g->zchunk[kPlain];
+                        HIPCHK(launch_step(a, g->st, kPlain, s));
+                        std::swap(A, B);
+                    }
+                    cur = -1;
+                    break;
+                case FD_ACT_YOUTURN: {
+                    const int n = act.step;
+                    if ((rc = bracket_step(n, A, B, out_f, brf,
+                                           (act.first && n >= 1) ? recb + (size_t)(n - 1) * sh->nrec : nullptr)))
+                        return rc;
+                    if (act.first) {   // n == nt-1: last trace row, then the residual
+                        Sample sm = make_sample(g, 1, sh->nrec, recb + (size_t)(nt - 1) * sh->nrec, 1.f);
+                        HIPCHK(launch_sample(sm, out_f, g->st, s));
+                        HIPCHK(launch_misfit(recb, d_obs, nres, given, resid, g->partials, kNPart, misfit, s));
+                    }
+                    if ((rc = adjoint_step(n + 1, brf))) return rc;
+                    break;
+                }
+                default:
+                    return fdi_fail(FD_ERR_STATE, "bad schedule action");
+            }
         }
     }
     HIPCHK(launch_field_to_dense_f64(L, gacc, grad_m, s));

@@ -18,3 +18,7 @@ int fdi_forward_zero_state(fd_grid *g, hipStream_t s);
 int fdi_forward_steps(fd_grid *g, const fd_shot *sh, int nt, int n0, int n1, float *rec_out,
                       void **ckpt, int K, hipStream_t s);
 int fdi_grid_device(const fd_grid *g);
+
+#include <vector>
+// Binomial checkpoint schedule (fd_checkpoint.cpp).
+int fdi_checkpoint_plan(int nt, int slots, std::vector<fd_ckpt_action> *actions, long long *fwd);

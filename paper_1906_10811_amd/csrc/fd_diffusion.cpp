@@ -22,6 +22,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 bool to_grid_desc(const fd_diffusion_desc *d, fd_grid_desc *g) {
     if (!d) return fdi_fail(FD_ERR_ARG, "null descriptor"), false;
     if (!(d->nu > 0.0) || !std::isfinite(d->nu)) return fdi_fail(FD_ERR_ARG, "nu must be > 0"), false;
+    if (d->time_block < 0) return fdi_fail(FD_ERR_ARG, "time_block must be >= 0"), false;
     memset(g, 0, sizeof *g);
     g->ndim = 2;
     g->shape[0] = d->shape[0];
@@ -91,10 +92,20 @@ extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, 
         (e = launch_zero_field(L, B, Store::F32, s)) != hipSuccess ||
         (e = launch_dense_to_field(L, u0, A, Store::F32, 1.f, s)) != hipSuccess)
         return fdi_fail(FD_ERR_DEVICE, "diffusion setup: %s", hipGetErrorString(e));
-    for (int n = 0; n < nt; ++n) {
-        if ((e = launch_diffuse2d(L, A, B, w0, wx, wz, s)) != hipSuccess)
-            return fdi_fail(FD_ERR_DEVICE, "diffusion step: %s", hipGetErrorString(e));
+    // temporal blocking: each launch advances up to `per` levels from a tile
+    // staged with an r*per halo (the thesis's OPS tiling / YASK wave-front
+    // tiling idea, Section 2.2 and 2.3.1, in LDS)
+    int per = diffuse2d_max_levels(L.r);
+    if (desc->time_block > 0) per = std::min(per, desc->time_block);
+    for (int n = 0; n < nt;) {
+        const int lev = std::min(per, nt - n);
+        if (per <= 1)
+            e = launch_diffuse2d(L, A, B, w0, wx, wz, s);
+        else
+            e = launch_diffuse2d_tb(L, A, B, w0, wx, wz, lev, s);
+        if (e != hipSuccess) return fdi_fail(FD_ERR_DEVICE, "diffusion step: %s", hipGetErrorString(e));
         std::swap(A, B);
+        n += lev;
     }
     if ((e = launch_field_to_dense(L, A, u_out, Store::F32, 1.f, s)) != hipSuccess)
         return fdi_fail(FD_ERR_DEVICE, "diffusion readback: %s", hipGetErrorString(e));

@@ -112,6 +112,10 @@ hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, S
 // (weights already multiplied by nu dt).
 hipError_t launch_diffuse2d(const Layout &L, const float *u, float *out, float w0, const float *wx,
                             const float *wz, hipStream_t s);
+// Temporally blocked variant: nlev (1 .. diffuse2d_max_levels(r)) steps per launch.
+int diffuse2d_max_levels(int r);
+hipError_t launch_diffuse2d_tb(const Layout &L, const float *u, float *out, float w0, const float *wx,
+                               const float *wz, int nlev, hipStream_t s);
 hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
                          float *resid, double *partials, int npart, double *out, hipStream_t s);
 hipError_t launch_zero_f64(double *p, long long n, hipStream_t s);

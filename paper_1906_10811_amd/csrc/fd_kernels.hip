@@ -592,11 +592,130 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d(const DiffArgs a) {
     }
 }
 
+// Temporally blocked diffusion: one launch advances `nlev` (<= 16/R) levels.
+// A workgroup stages its 64 x 64 output tile plus an H = R*nlev halo (zero
+// outside the grid) in one LDS buffer and updates it in place level by
+// level on the shrinking region that stays exact: level t is computed on
+// rows and 4-point groups at least R*t from the staged border (rounded out
+// to whole groups; the rounding margin holds values that nothing exact
+// reads).  Between levels each lane keeps its new values in registers
+// across a barrier, so one buffer suffices.  HBM traffic: 8 B per point per
+// launch, i.e. 8/nlev B per point and step.
+constexpr int kTbHalo = 16;                        // R * levels per launch, at most
+constexpr int kTbRows = kTile2Z + 2 * kTbHalo;     // 96 staged rows
+constexpr int kTbPadX = 4;                         // zero floats left/right of a staged row
+constexpr int kTbW4 = (kTileX + 2 * kTbHalo + 2 * kTbPadX) / 4;   // float4 per staged row
+constexpr int kTbGroups = (kTileX + 2 * kTbHalo) / 4 * kTbRows;   // 4-point groups of level 1 at most
+constexpr int kTbPerLane = (kTbGroups + kBlock - 1) / kBlock;
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int nlev) {
+    __shared__ float4 lds[kTbRows * kTbW4];
+    const Layout L = a.L;
+    const int t0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int bx = t0 % a.ntx, bz = t0 / a.ntx;
+    const int H = R * nlev;                       // staged halo of this launch
+    const int x0 = bx * kTileX - H, z0 = bz * kTile2Z - H;   // grid coords of staged (0, 0)
+    const int rows = kTile2Z + 2 * H;
+    const int g4 = (kTileX + 2 * H) / 4 + 2;      // staged float4 per row incl. pads
+    const int lane = (int)threadIdx.x;
+    // stage level 0; float4 column c covers grid x = x0 - 4 + 4c (a float4
+    // load when that is 16-B aligned in the grid, else element by element)
+    for (int i = lane; i < rows * g4; i += kBlock) {
+        const int lr = i / g4, c = i - lr * g4;
+        const int gz = z0 + lr, gx = x0 - kTbPadX + 4 * c;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gz >= 0 && gz < L.nz && gx + 3 >= 0 && gx < L.nx) {
+            if (gx >= 0 && (gx & 3) == 0) {
+                v = *reinterpret_cast<const float4 *>(a.u + L.offset(gx, 0, gz));
+            } else {
+                float e[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int xx = gx + k;
+                    e[k] = (xx >= 0 && xx < L.nx) ? a.u[L.offset(xx, 0, gz)] : 0.f;
+                }
+                v = make_float4(e[0], e[1], e[2], e[3]);
+            }
+        }
+        lds[lr * kTbW4 + c] = v;
+    }
+    __syncthreads();
+    const float *ldsf = reinterpret_cast<const float *>(lds);
+    for (int t = 1; t <= nlev; ++t) {
+        // level t region: rows [R t, rows - R t), floats [PadX + 4 floor(R t / 4), ...) in groups of 4
+        const int r0 = R * t, r1 = rows - R * t;
+        const int c0 = 1 + (R * t) / 4;                        // first float4 column (pad column is 0)
+        const int c1 = 1 + (kTileX + 2 * H - R * t + 3) / 4;   // one past the last
+        const int ncol = c1 - c0, nrow = r1 - r0;
+        float4 res[kTbPerLane];
+#pragma unroll
+        for (int k = 0; k < kTbPerLane; ++k) {
+            const int gidx = lane + k * kBlock;
+            res[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gidx < ncol * nrow) {
+                const int lr = r0 + gidx / ncol, c = c0 + gidx % ncol;
+                const float *rowp = ldsf + (lr * kTbW4 + c) * 4;   // first of the group's 4 floats
+                float un[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) un[i] = a.w0 * rowp[i];
+#pragma unroll
+                for (int j = 1; j <= R; ++j) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float acc = a.wx[j] * (rowp[i + j] + rowp[i - j]);
+                        acc += a.wz[j] * (rowp[i + j * kTbW4 * 4] + rowp[i - j * kTbW4 * 4]);
+                        un[i] += acc;
+                    }
+                }
+                const int gz = z0 + lr;
+                const int gx = x0 - kTbPadX + 4 * c;
+                float o[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bool in = gz >= 0 && gz < L.nz && gx + i >= 0 && gx + i < L.nx;
+                    o[i] = in ? un[i] + rowp[i] : 0.f;   // the field is zero outside the grid
+                }
+                res[k] = make_float4(o[0], o[1], o[2], o[3]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kTbPerLane; ++k) {
+            const int gidx = lane + k * kBlock;
+            if (gidx < ncol * nrow) {
+                const int lr = r0 + gidx / ncol, c = c0 + gidx % ncol;
+                lds[lr * kTbW4 + c] = res[k];
+            }
+        }
+        __syncthreads();
+    }
+    // write the 64 x 64 tile
+    for (int i = lane; i < kTile2Z * (kTileX / 4); i += kBlock) {
+        const int lr = i / (kTileX / 4), cq = i - lr * (kTileX / 4);
+        const int gz = z0 + H + lr, gx = x0 + H + 4 * cq;
+        if (gz >= L.nz || gx >= L.nx) continue;
+        const float *src = ldsf + (H + lr) * kTbW4 * 4 + kTbPadX + H + 4 * cq;
+        const int nvalid = L.nx - gx;
+        const long long off = L.offset(gx, 0, gz);
+        if (nvalid >= 4) {
+            st4nt_f32(a.out + off, make_float4(src[0], src[1], src[2], src[3]));
+        } else {
+            for (int k = 0; k < nvalid; ++k) a.out[off + k] = src[k];
+        }
+    }
+}
+
 template <int... Rs>
 struct DiffTable {
     static void (*get(int r))(const DiffArgs) {
         void (*f)(const DiffArgs) = nullptr;
         ((r == Rs ? (f = k_diffuse2d<Rs>, 0) : 0), ...);
+        return f;
+    }
+    static void (*get_tb(int r))(const DiffArgs, int) {
+        void (*f)(const DiffArgs, int) = nullptr;
+        ((r == Rs ? (f = k_diffuse2d_tb<Rs>, 0) : 0), ...);
         return f;
     }
 };
@@ -895,6 +1014,27 @@ hipError_t launch_diffuse2d(const Layout &L, const float *u, float *out, float w
     a.ntx = (L.nx + kTileX - 1) / kTileX;
     a.ntz = (L.nz + kTile2Z - 1) / kTile2Z;
     hipLaunchKernelGGL(f, dim3(a.ntx * a.ntz), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int diffuse2d_max_levels(int r) { return kTbHalo / r; }
+
+hipError_t launch_diffuse2d_tb(const Layout &L, const float *u, float *out, float w0, const float *wx,
+                               const float *wz, int nlev, hipStream_t s) {
+    auto f = DiffTable<1, 2, 3, 4, 5, 6, 7, 8>::get_tb(L.r);
+    if (!f || L.ndim != 2 || nlev < 1 || L.r * nlev > kTbHalo) return hipErrorInvalidValue;
+    DiffArgs a{};
+    a.L = L;
+    a.u = u;
+    a.out = out;
+    a.w0 = w0;
+    for (int j = 0; j <= kMaxR; ++j) {
+        a.wx[j] = wx[j];
+        a.wz[j] = wz[j];
+    }
+    a.ntx = (L.nx + kTileX - 1) / kTileX;
+    a.ntz = (L.nz + kTile2Z - 1) / kTile2Z;
+    hipLaunchKernelGGL(f, dim3(a.ntx * a.ntz), dim3(kBlock), 0, s, a, nlev);
     return hipGetLastError();
 }
 

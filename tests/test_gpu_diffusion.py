@@ -22,7 +22,11 @@ def _hat(nx, ny, seed):
 
 
 @pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 16])
-def test_diffusion_parity(so):
+@pytest.mark.parametrize("time_block", [0, 1, 3])
+def test_diffusion_parity(so, time_block):
+    """203 x 141 (ragged 64 x 64 tiles), 121 steps: one step per launch, 3
+    per launch, or as many as the tile halo allows (16 / (so/2), with a
+    shorter last launch)."""
     need_gpu()
     from paper_1906_10811_amd import diffusion
     nx, ny, h = 203, 141, (1.0 / 202, 1.0 / 140)
@@ -30,11 +34,11 @@ def test_diffusion_parity(so):
     nu = 0.5
     dt = 0.8 * oracle.diffusion_critical_dt(g, nu)
     u0 = _hat(nx, ny, so)
-    want = oracle.diffusion(g, u0, nu, dt, 120)
-    got = diffusion(torch.from_numpy(u0).float().cuda(), h, so, nu, dt, 120)
+    want = oracle.diffusion(g, u0, nu, dt, 121)
+    got = diffusion(torch.from_numpy(u0).float().cuda(), h, so, nu, dt, 121, time_block=time_block)
     torch.cuda.synchronize()
     e = rel_l2(got.cpu().numpy(), want)
-    print("diffusion so=%d rel L2 %.3e" % (so, e))
+    print("diffusion so=%d time_block=%d rel L2 %.3e" % (so, time_block, e))
     assert e <= 1e-5
 
 
@@ -48,7 +52,7 @@ def test_diffusion_full_size(n):
     nu = 0.5
     dt = 0.8 * oracle.diffusion_critical_dt(g, nu)
     u0 = _hat(n, n, 3).astype(np.float32)
-    nt = 3
+    nt = 5
     got = diffusion(torch.from_numpy(u0).cuda(), h, so, nu, dt, nt)
     torch.cuda.synchronize()
     got = got.cpu().numpy()

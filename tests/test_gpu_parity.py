@@ -187,6 +187,30 @@ def test_gradient_parity(K):
     assert eg <= 1e-4
 
 
+@pytest.mark.parametrize("slots", [0, 3, 9])
+def test_gradient_binomial_schedule(slots):
+    """The binomial checkpoint schedule (snapshot slots 0, 3, 9) reproduces
+    the fixed-interval gradient, misfit, traces and F^T residual: the same
+    kernels compute the same levels, only the order of recomputation
+    differs."""
+    need_gpu()
+    c, vp, sig, d_obs = _gradient_case()
+    g = gpu_grid(c)
+    dev = torch.device("cuda:0")
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    obs = torch.from_numpy(d_obs).to(dev)
+    m1, g1, r1, a1 = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=50, want_src_adj=True)
+    m2, g2, r2, a2 = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], binomial_slots=slots, want_src_adj=True)
+    torch.cuda.synchronize()
+    eg = rel_l2(g2.cpu().numpy(), g1.cpu().numpy())
+    _print("binomial slots=%d" % slots, grad=eg, misfit=abs(m2.item() - m1.item()) / m1.item(),
+           traces_bitwise=int(torch.equal(r1, r2)), grad_bitwise=int(torch.equal(g1, g2)))
+    assert torch.equal(r1, r2)
+    assert abs(m2.item() - m1.item()) <= 1e-14 * m1.item()
+    assert eg <= 1e-12
+    assert rel_l2(a2.cpu().numpy(), a1.cpu().numpy()) <= 1e-12
+
+
 def test_gradient_finite_differences_on_gpu():
     """<g_m, dm> from fd_gradient against central differences of the misfit
     computed by fd_forward on the padded grid, float32 throughout.  The data
