@@ -67,20 +67,21 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=False)
+        src = os.path.join(_HERE, "fd_oracle.c")
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+            build(force=True)
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         lib.orc_laplacian.argtypes = [ctypes.c_int, P, P, ctypes.c_int, P, P, P]
         lib.orc_laplacian.restype = None
         lib.orc_forward.argtypes = [ctypes.c_int, P, P, ctypes.c_int, P, P, P,
                                     ctypes.c_double, ctypes.c_int,
-                                    ctypes.c_int, P, P, P,
+                                    ctypes.c_int, ctypes.c_int, P, P, P,
                                     ctypes.c_int, P, P, P, P, P, P]
         lib.orc_forward.restype = ctypes.c_int
         lib.orc_adjoint.argtypes = [ctypes.c_int, P, P, ctypes.c_int, P, P, P,
                                     ctypes.c_double, ctypes.c_int,
-                                    ctypes.c_int, P, P, P,
+                                    ctypes.c_int, ctypes.c_int, P, P, P,
                                     ctypes.c_int, P, P, P, P]
         lib.orc_adjoint.restype = ctypes.c_int
         lib.orc_imaging.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_int,
@@ -225,12 +226,46 @@ def courant_dt(g: Grid, vmax: float, courant: float = 0.4) -> float:
 # --------------------------------------------------------------------------
 # O8 / O9: multilinear weights of off-grid points
 # --------------------------------------------------------------------------
-def sparse_weights(g: Grid, coords) -> tuple:
-    """Flat padded indices and weights of the 2^d corners of the cell that
-    contains each point.  Per axis t = (x - o)/h, cell k = floor(t) (k = N-2
-    when the point sits on the last grid line), p = t - k; the corner weight
-    is the product over axes of (1 - p) or p.  Raises ValueError for points
-    outside the physical extent."""
+def kaiser_beta_default(r: int) -> float:
+    """Kaiser shape used when none is given: b = pi r / 2 (a reading; Hicks
+    2002 tunes b per half-width for a chosen passband, the thesis does not
+    treat off-grid points at all)."""
+    return math.pi * r / 2.0
+
+
+def kaiser_sinc_1d(t: float, r: int, b: float = 0.0) -> tuple:
+    """Kaiser-windowed sinc weights of a point at fractional grid position t
+    along one axis (Hicks 2002): the 2r nodes k = floor(t) - r + 1 ..
+    floor(t) + r, weight sinc(k - t) W(k - t) with the Kaiser window
+    W(x) = I0(b sqrt(1 - (x/r)^2)) / I0(b) for |x| <= r, else 0.
+    Returns (first node, list of the 2r weights)."""
+    b = b if b > 0.0 else kaiser_beta_default(r)
+    k0 = int(math.floor(t)) - r + 1
+    w = []
+    for i in range(2 * r):
+        x = (k0 + i) - t
+        if x == round(x):            # sinc is exactly 1 at 0 and 0 at the other integers
+            sinc = 1.0 if x == 0.0 else 0.0
+        else:
+            sinc = math.sin(math.pi * x) / (math.pi * x)
+        q = 1.0 - (x / r) ** 2
+        win = float(np.i0(b * math.sqrt(q))) / float(np.i0(b)) if q >= 0.0 else 0.0
+        w.append(sinc * win)
+    return k0, w
+
+
+def sparse_weights(g: Grid, coords, sinc_radius: int = 0, sinc_beta: float = 0.0) -> tuple:
+    """Flat padded indices and weights of the grid points a sparse point
+    touches.  sinc_radius 0 (O8): multilinear over the 2^d corners of the
+    cell that contains the point: per axis t = (x - o)/h, cell k = floor(t)
+    (k = N-2 when the point sits on the last grid line), p = t - k, corner
+    weight the product over axes of (1 - p) or p.  sinc_radius r >= 1: the
+    tensor product over axes of kaiser_sinc_1d(t, r, sinc_beta), (2r)^d
+    nodes; a node outside the padded grid keeps index 0 and weight 0 (the
+    field is zero there, so dropping it is the exact restriction).  Raises
+    ValueError for points outside the physical extent."""
+    if sinc_radius:
+        return _sinc_weights(g, coords, sinc_radius, sinc_beta)
     xyz = np.asarray(coords, dtype=np.float64).reshape(-1, g.ndim)
     npts = xyz.shape[0]
     nc = 1 << g.ndim
@@ -262,6 +297,39 @@ def sparse_weights(g: Grid, coords) -> tuple:
                 wt *= fr[a] if b else (1.0 - fr[a])
             idx[p_i, ci] = flat
             w[p_i, ci] = wt
+    return idx, w
+
+
+def _sinc_weights(g: Grid, coords, r: int, b: float) -> tuple:
+    xyz = np.asarray(coords, dtype=np.float64).reshape(-1, g.ndim)
+    npts = xyz.shape[0]
+    nc = (2 * r) ** g.ndim
+    idx = np.zeros((npts, nc), dtype=np.int64)
+    w = np.zeros((npts, nc), dtype=np.float64)
+    strides = []
+    s = 1
+    for a in range(g.ndim):
+        strides.append(s)
+        s *= g.padded[a]
+    for p_i in range(npts):
+        axes = []
+        for a in range(g.ndim):
+            t = (xyz[p_i, a] - g.origin[a]) / g.spacing[a]
+            if not (0.0 <= t <= g.shape[a] - 1):
+                raise ValueError("point %d outside the grid along axis %d" % (p_i, a))
+            axes.append(kaiser_sinc_1d(t, r, b))
+        for ci, offs in enumerate(product(range(2 * r), repeat=g.ndim)):
+            flat, wt, inside = 0, 1.0, True
+            for a in range(g.ndim):
+                k0, wa = axes[a]
+                ip = k0 + offs[a] + g.nbl
+                if not 0 <= ip < g.padded[a]:
+                    inside = False
+                flat += ip * strides[a]
+                wt *= wa[offs[a]]
+            if inside:
+                idx[p_i, ci] = flat
+                w[p_i, ci] = wt
     return idx, w
 
 
@@ -297,7 +365,7 @@ def _field(g, a, name):
 
 
 def forward(g: Grid, v_pad, sigma, dt: float, nt: int, src_coords, wavelet,
-            rec_coords, u0=None, u_prev=None, keep_history: bool = False):
+            rec_coords, u0=None, u_prev=None, keep_history: bool = False, sinc_radius: int = 0, sinc_beta: float = 0.0):
     """O6 + O8 + O9.  Returns (rec [nt, nrec], u^nt, u^{nt-1}, history or None).
     wavelet is [nt, nsrc]; history holds u^{-1}..u^{nt} when requested."""
     _check_grid(g)
@@ -305,9 +373,10 @@ def forward(g: Grid, v_pad, sigma, dt: float, nt: int, src_coords, wavelet,
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
     if v_pad.shape != g.array_shape or sigma.shape != g.array_shape:
         raise ValueError("medium shape")
-    sidx, sw = sparse_weights(g, src_coords)
-    ridx, rw = sparse_weights(g, rec_coords)
+    sidx, sw = sparse_weights(g, src_coords, sinc_radius, sinc_beta)
+    ridx, rw = sparse_weights(g, rec_coords, sinc_radius, sinc_beta)
     nsrc, nrec = sidx.shape[0], ridx.shape[0]
+    nc = sidx.shape[1]
     wav = np.ascontiguousarray(wavelet, dtype=np.float64).reshape(nt, nsrc)
     rec = np.zeros((nt, nrec), dtype=np.float64)
     a = _field(g, u0, "u0")
@@ -319,7 +388,7 @@ def forward(g: Grid, v_pad, sigma, dt: float, nt: int, src_coords, wavelet,
     c = fd_weights(g.space_order)
     rc = _load().orc_forward(g.ndim, _ptr(n), _ptr(h), g.radius, _ptr(c),
                              _ptr(v_pad), _ptr(sigma), float(dt), int(nt),
-                             nsrc, _ptr(sidx), _ptr(sw), _ptr(wav),
+                             nc, nsrc, _ptr(sidx), _ptr(sw), _ptr(wav),
                              nrec, _ptr(ridx), _ptr(rw), _ptr(rec),
                              _ptr(a), _ptr(b),
                              _ptr(hist) if hist is not None else None)
@@ -329,14 +398,15 @@ def forward(g: Grid, v_pad, sigma, dt: float, nt: int, src_coords, wavelet,
 
 
 def adjoint(g: Grid, v_pad, sigma, dt: float, nt: int, src_coords, rec_coords,
-            residual, keep_history: bool = False):
+            residual, keep_history: bool = False, sinc_radius: int = 0, sinc_beta: float = 0.0):
     """O11.  residual is [nt, nrec]; returns (F^T r [nt, nsrc], lam history or None)."""
     _check_grid(g)
     v_pad = np.ascontiguousarray(v_pad, dtype=np.float64)
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
-    sidx, sw = sparse_weights(g, src_coords)
-    ridx, rw = sparse_weights(g, rec_coords)
+    sidx, sw = sparse_weights(g, src_coords, sinc_radius, sinc_beta)
+    ridx, rw = sparse_weights(g, rec_coords, sinc_radius, sinc_beta)
     nsrc, nrec = sidx.shape[0], ridx.shape[0]
+    nc = sidx.shape[1]
     res = np.ascontiguousarray(residual, dtype=np.float64).reshape(nt, nrec)
     out = np.zeros((nt, nsrc), dtype=np.float64)
     hist = np.zeros((nt,) + g.array_shape, dtype=np.float64) if keep_history else None
@@ -344,7 +414,7 @@ def adjoint(g: Grid, v_pad, sigma, dt: float, nt: int, src_coords, rec_coords,
     c = fd_weights(g.space_order)
     rc = _load().orc_adjoint(g.ndim, _ptr(n), _ptr(h), g.radius, _ptr(c),
                              _ptr(v_pad), _ptr(sigma), float(dt), int(nt),
-                             nsrc, _ptr(sidx), _ptr(sw), _ptr(out),
+                             nc, nsrc, _ptr(sidx), _ptr(sw), _ptr(out),
                              nrec, _ptr(ridx), _ptr(rw), _ptr(res),
                              _ptr(hist) if hist is not None else None)
     if rc != 0:
@@ -359,13 +429,14 @@ def misfit(rec, d_obs) -> tuple:
 
 
 def gradient(g: Grid, v_pad, sigma, dt: float, nt: int, src_coords, wavelet,
-             rec_coords, d_obs):
+             rec_coords, d_obs, sinc_radius: int = 0, sinc_beta: float = 0.0):
     """O12: returns (J, g_m on the padded grid, rec).  Keeps the whole forward
     and adjoint history in memory: small problems only."""
     rec, _, _, hist = forward(g, v_pad, sigma, dt, nt, src_coords, wavelet,
-                              rec_coords, keep_history=True)
+                              rec_coords, keep_history=True, sinc_radius=sinc_radius, sinc_beta=sinc_beta)
     J, r = misfit(rec, d_obs)
-    _, lam = adjoint(g, v_pad, sigma, dt, nt, src_coords, rec_coords, r, keep_history=True)
+    _, lam = adjoint(g, v_pad, sigma, dt, nt, src_coords, rec_coords, r, keep_history=True,
+                     sinc_radius=sinc_radius, sinc_beta=sinc_beta)
     grad = np.zeros(g.array_shape, dtype=np.float64)
     n, _ = _dims(g)
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
@@ -387,9 +458,9 @@ def energy(g: Grid, v_pad, dt: float, u_next, u_cur) -> float:
 # --------------------------------------------------------------------------
 def diffusion(g: Grid, u0, nu: float, dt: float, nt: int) -> np.ndarray:
     """Explicit diffusion u_t = nu (u_xx + u_yy), first order in time: the
-    operator Section 5.1.2 benchmarks (solve(Eq(u.dt, nu*(u.dx2 + u.dy2)),
-    u.forward)), u^{n+1} = u^n + nu dt Lap_h u^n with the O3 weights and the
-    field zero outside the grid.  Returns u^{nt}."""
+    operator the benchmarks of Section 5.1.2 time, advanced by forward Euler,
+    u^{n+1} = u^n + nu dt Lap_h u^n, with the O3 weights and the field zero
+    outside the grid.  Returns u^{nt}."""
     if g.ndim != 2 or g.nbl != 0:
         raise ValueError("diffusion is defined on a 2D grid without damping layer")
     u = np.array(u0, dtype=np.float64, copy=True)

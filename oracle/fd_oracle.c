@@ -93,8 +93,10 @@ static void leapfrog(long tot, double dt, const double *vel, const double *sigma
 
 /*
  * Forward modelling, O6 + O8 + O9.
- *   nc = 2^ndim corners per sparse point; src_idx/src_w are [nsrc][nc]
- *   (flat padded index, multilinear weight), rec_idx/rec_w likewise.
+ *   nc grid points per sparse point (2^ndim multilinear corners, or (2r)^ndim
+ *   windowed-sinc nodes); src_idx/src_w are [nsrc][nc] (flat padded index,
+ *   weight; weight 0 for nodes dropped outside the grid), rec_idx/rec_w
+ *   likewise.
  *   wavelet is [nt][nsrc]; sample n enters u^{n+1} as
  *   q = sum_s w_s[n] W_s / prod(h)   (discrete delta, O8).
  *   rec[n][r] = sum_c W_{r,c} u^{n+1}[idx_{r,c}]   (O9), n = 0..nt-1.
@@ -104,12 +106,11 @@ static void leapfrog(long tot, double dt, const double *vel, const double *sigma
  */
 int orc_forward(int ndim, const long *n, const double *h, int r, const double *c,
                 const double *vel, const double *sigma, double dt, int nt,
-                int nsrc, const long *src_idx, const double *src_w, const double *wavelet,
+                int nc, int nsrc, const long *src_idx, const double *src_w, const double *wavelet,
                 int nrec, const long *rec_idx, const double *rec_w, double *rec,
                 double *u_cur, double *u_prev, double *history)
 {
     const long tot = total_points(ndim, n);
-    const int nc = 1 << ndim;
     double cell = 1.0;
     for (int a = 0; a < ndim; ++a) cell *= h[a];
 
@@ -159,12 +160,11 @@ int orc_forward(int ndim, const long *n, const double *h, int r, const double *c
  */
 int orc_adjoint(int ndim, const long *n, const double *h, int r, const double *c,
                 const double *vel, const double *sigma, double dt, int nt,
-                int nsrc, const long *src_idx, const double *src_w, double *src_out,
+                int nc, int nsrc, const long *src_idx, const double *src_w, double *src_out,
                 int nrec, const long *rec_idx, const double *rec_w, const double *residual,
                 double *lam_hist)
 {
     const long tot = total_points(ndim, n);
-    const int nc = 1 << ndim;
     double cell = 1.0;
     for (int a = 0; a < ndim; ++a) cell *= h[a];
 

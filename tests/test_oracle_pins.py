@@ -189,6 +189,123 @@ def test_sparse_weights_on_grid_and_outside():
         oracle.sparse_weights(g, [(0.0, -1e-9)])
 
 
+# ------------------------------------- windowed-sinc sparse points (Hicks 2002)
+@pytest.mark.parametrize("r", [1, 2, 4, 8])
+def test_sinc_weights_on_grid_are_a_delta(r):
+    """An on-grid point: sinc vanishes at every other integer, so the 2r nodes
+    reduce to the point itself, exactly as the multilinear weights do."""
+    g = oracle.Grid((30, 28), (10.0, 10.0), (0.0, 0.0), 4, nbl=3)
+    i1, w1 = oracle.sparse_weights(g, [(120.0, 90.0)], sinc_radius=r)
+    i0, w0 = oracle.sparse_weights(g, [(120.0, 90.0)])
+    assert np.count_nonzero(w1) == 1 and w1.max() == 1.0
+    assert i1[0, np.argmax(w1[0])] == i0[0, np.argmax(w0[0])]
+
+
+@pytest.mark.parametrize("r", [1, 3, 4])
+def test_sinc_weights_mirror_symmetry(r):
+    """The kernel is even: the weights at fraction f, read backwards, are the
+    weights at fraction 1 - f.  A node window shifted by one (floor(t) - r
+    instead of floor(t) - r + 1) breaks this."""
+    for f in (0.1, 0.37, 0.5, 0.81):
+        k0a, wa = oracle.kaiser_sinc_1d(7.0 + f, r)
+        k0b, wb = oracle.kaiser_sinc_1d(7.0 + 1.0 - f, r)
+        assert k0a == 7 - r + 1 and k0b == k0a
+        assert np.allclose(wa, wb[::-1], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("r,bound", [(3, 1e-2), (4, 2e-3), (6, 1e-4)])
+def test_sinc_weights_interpolate_band_limited_signals(r, bound):
+    """Interpolating cos(kx + phi) at random off-grid points: with k h up to
+    pi/2 (four points per wavelength) the windowed sinc of half-width r
+    reproduces the exact value within `bound` (the accuracy class Hicks
+    reports), while the multilinear weights are off by up to ~0.3."""
+    rng = np.random.default_rng(3)
+    worst, worst_lin = 0.0, 0.0
+    for kh in (0.0, 0.25 * math.pi, 0.5 * math.pi):
+        for _ in range(100):
+            t, ph = rng.uniform(20, 21), rng.uniform(0, 2 * math.pi)
+            k0, w = oracle.kaiser_sinc_1d(t, r)
+            got = float(np.dot(w, np.cos(kh * np.arange(k0, k0 + 2 * r) + ph)))
+            worst = max(worst, abs(got - math.cos(kh * t + ph)))
+            f = t - math.floor(t)
+            lin = (1 - f) * math.cos(kh * math.floor(t) + ph) + f * math.cos(kh * (math.floor(t) + 1) + ph)
+            worst_lin = max(worst_lin, abs(lin - math.cos(kh * t + ph)))
+    assert worst <= bound
+    assert worst_lin > 0.2
+
+
+def test_sinc_weights_at_boundary_drop_outside_nodes():
+    """Near the edge of the padded grid the nodes outside it carry weight 0
+    and the nodes inside keep the weights the same fraction has in the
+    interior (the 3D tensor product is translation invariant)."""
+    g = oracle.Grid((20, 18, 16), (10.0, 10.0, 10.0), (0.0, 0.0, 0.0), 4, nbl=1)
+    r = 4
+    edge = (3.3, 41.6, 150.0 - 2.2)      # x near the low edge, z near the high edge
+    inner = (83.3, 41.6, 70.0 - 2.2)     # same fractions, 8 cells in from both
+    ie, we = oracle.sparse_weights(g, [edge], sinc_radius=r)
+    ii, wi = oracle.sparse_weights(g, [inner], sinc_radius=r)
+    we, wi = we.reshape(2 * r, 2 * r, 2 * r), wi.reshape(2 * r, 2 * r, 2 * r)   # (x, y, z) node offsets
+    # node x offsets -3..4 about floor: with nbl 1 the padded index is 0..; x
+    # nodes 0 - 3 + 1 + 1 = -1 .. : the first one falls outside
+    inside_x = np.array([k0 + 1 >= 0 for k0 in range(-3, 5)])
+    nzp = g.padded[2]
+    inside_z = np.array([14 - 3 + i + 1 < nzp for i in range(2 * r)])
+    mask = inside_x[:, None, None] & inside_z[None, None, :] & np.ones((1, 2 * r, 1), bool)
+    assert (we[~mask] == 0).all() and mask.sum() < mask.size
+    assert np.allclose(we[mask], wi[mask], rtol=1e-12, atol=1e-18)
+    assert ie.min() >= 0 and ie.max() < np.prod(g.array_shape)
+
+
+def test_sinc_source_is_superposition_of_point_sources():
+    """Brute force: a windowed-sinc source radiates the weighted sum of the
+    fields of on-grid point sources at its nodes (each run through the
+    multilinear path, where an on-grid point is a delta), and a sinc receiver
+    records the weighted sum of on-grid receivers at its nodes."""
+    g, vp, sig, dt = _hetero_setup(2)
+    nt, r = 70, 2
+    wav = synth.ricker(nt, dt, 25.0)[:, None]
+    S = (5.0 + 91.3, -3.0 + 70.6)
+    R_ = (5.0 + 150.8, -3.0 + 97.1)
+    got, *_ = oracle.forward(g, vp, sig, dt, nt, [S], wav, [R_], sinc_radius=r)
+    on_grid = []
+    for pt in (S, R_):
+        ts = [(c - o) / h for c, o, h in zip(pt, g.origin, g.spacing)]
+        ax = [oracle.kaiser_sinc_1d(t, r) for t in ts]
+        on_grid.append([((g.origin[0] + (ax[0][0] + i) * g.spacing[0], g.origin[1] + (ax[1][0] + j) * g.spacing[1]),
+                         ax[0][1][i] * ax[1][1][j]) for i in range(2 * r) for j in range(2 * r)])
+    rec_pts = [p for p, _ in on_grid[1]]
+    rec_w = np.array([w for _, w in on_grid[1]])
+    want = np.zeros(nt)
+    for p, ws in on_grid[0]:
+        tr, *_ = oracle.forward(g, vp, sig, dt, nt, [p], wav, rec_pts)
+        want += ws * (tr @ rec_w)
+    assert np.linalg.norm(want) > 0
+    assert np.linalg.norm(got[:, 0] - want) <= 1e-12 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_sinc_reciprocity_and_dot_product(ndim):
+    """The operator with windowed-sinc sources and receivers keeps the two
+    identities the multilinear one has: source-receiver reciprocity and
+    <F w, d> = <w, F^T d>."""
+    g, vp, sig, dt = _hetero_setup(ndim)
+    nt, r = 50, 3 if ndim == 2 else 2
+    rng = np.random.default_rng(8)
+    ext = [(n - 1) * hh for n, hh in zip(g.shape, g.spacing)]
+    pts = [tuple(o + rng.uniform(0.1, 0.9) * e for o, e in zip(g.origin, ext)) for _ in range(5)]
+    wav = synth.ricker(nt, dt, 25.0)[:, None]
+    rab, *_ = oracle.forward(g, vp, sig, dt, nt, [pts[0]], wav, [pts[1]], sinc_radius=r)
+    rba, *_ = oracle.forward(g, vp, sig, dt, nt, [pts[1]], wav, [pts[0]], sinc_radius=r)
+    assert np.linalg.norm(rab) > 0
+    assert np.linalg.norm(rab - rba) <= 1e-12 * np.linalg.norm(rab)
+    w = rng.standard_normal((nt, 2))
+    d = rng.standard_normal((nt, 3))
+    Fw, *_ = oracle.forward(g, vp, sig, dt, nt, pts[:2], w, pts[2:], sinc_radius=r)
+    Ftd, _ = oracle.adjoint(g, vp, sig, dt, nt, pts[:2], pts[2:], d, sinc_radius=r)
+    lhs, rhs = float(np.sum(Fw * d)), float(np.sum(w * Ftd))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+
+
 # ---------------------------------------------------------- damping (O5)
 def test_damping_profile():
     g = oracle.Grid((10, 8, 6), (10.0, 10.0, 10.0), (0.0, 0.0, 0.0), 4, nbl=4)
