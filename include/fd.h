@@ -25,6 +25,12 @@
  *   sigma(i) = damp_max * sum_a (d_a/nbl)^2, d_a = distance into the layer.
  *   q^n = sum_s w_s[n] W_s / prod(h)  (multilinear weights W over the 2^d
  *   corners of the cell holding the source); rec_r[n] = sum W_r u^{n+1}.
+ *   With sinc_radius r > 0, W is instead the tensor product over axes of
+ *   Kaiser-windowed sinc weights on the 2r nodes around the point (Hicks,
+ *   Geophysics 67(1), 2002): for a node at signed distance x (in cells),
+ *   sinc(x) I0(b sqrt(1 - (x/r)^2)) / I0(b); nodes outside the padded grid
+ *   are dropped (the field is zero there).  Injection stays the transpose
+ *   of interpolation, so the adjoint below stays exact.
  *
  * Conventions shared by every call:
  *   - Return FD_OK (0) or a negative fd_status; fd_last_error() gives a
@@ -87,6 +93,9 @@ typedef struct fd_grid_desc {
     int max_src;           /* capacity of the source table (points), 0 selects 64 */
     int max_rec;           /* capacity of the receiver table (points), 0 selects 4096 */
     int zchunk;            /* planes marched per workgroup in 3D, 0 selects automatically */
+    int sinc_radius;       /* 0: multilinear sparse weights; 1..8: Kaiser-windowed sinc
+                              over (2 sinc_radius)^ndim nodes per point */
+    double sinc_beta;      /* Kaiser shape b; <= 0 selects pi * sinc_radius / 2 */
 } fd_grid_desc;
 
 /* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
@@ -279,8 +288,10 @@ typedef struct fd_diffusion_desc {
     double spacing[2];     /* h_x, h_y > 0 */
     int space_order;       /* even, 2..16 */
     double nu;             /* diffusivity > 0 */
-    int time_block;        /* steps per launch: 0 = as many as the tile halo allows
-                              (16 / (so/2)), 1 = one step per launch, k = at most k */
+    int time_block;        /* steps per launch: 0 = automatic (16 / (so/2) for
+                              so <= 4, where the LDS-blocked kernel beats one
+                              step per launch, else 1), 1 = one step per launch,
+                              k > 1 = at most min(k, 16 / (so/2)) */
 } fd_diffusion_desc;
 
 /* Device workspace for fd_diffusion_run (two pitched float32 fields). */

@@ -54,7 +54,7 @@ class Grid:
     def __init__(self, shape, spacing, vp: torch.Tensor, space_order: int = 8, nbl: int = 0,
                  origin=None, damp_max: float = 0.0, storage: str = "f32", amp_scale: float = 0.0,
                  vp_padded: bool = False, max_src: int = 0, max_rec: int = 0, zchunk: int = 0,
-                 stream=None):
+                 sinc_radius: int = 0, sinc_beta: float = 0.0, stream=None):
         lib = _lib.load()
         ndim = len(shape)
         self.ndim = ndim
@@ -73,6 +73,8 @@ class Grid:
         d.max_src = int(max_src)
         d.max_rec = int(max_rec)
         d.zchunk = int(zchunk)
+        d.sinc_radius = int(sinc_radius)
+        d.sinc_beta = float(sinc_beta)
         self.desc = d
         nbytes = ctypes.c_size_t()
         _lib.check(lib.fd_grid_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
@@ -262,7 +264,7 @@ class Server:
 
     @staticmethod
     def _request(shape, spacing, space_order, nbl, vp, src_xyz, wavelet, rec_xyz, dt, storage="f32",
-                 origin=None, amp_scale=0.0):
+                 origin=None, amp_scale=0.0, sinc_radius=0, sinc_beta=0.0):
         ndim = len(shape)
         r = _lib.Request()
         g = r.grid
@@ -275,6 +277,8 @@ class Server:
         g.nbl = int(nbl)
         g.storage = _STORAGE[storage]
         g.amp_scale = float(amp_scale)
+        g.sinc_radius = int(sinc_radius)
+        g.sinc_beta = float(sinc_beta)
         vp = np.ascontiguousarray(vp, dtype=np.float32)
         src = _coords(src_xyz, ndim)
         rec = _coords(rec_xyz, ndim)
@@ -340,7 +344,7 @@ def diffusion(u0: torch.Tensor, spacing, space_order: int, nu: float, dt: float,
               out: torch.Tensor | None = None, time_block: int = 0, stream=None) -> torch.Tensor:
     """fd_diffusion_run: nt explicit steps of u_t = nu (u_xx + u_yy) from the
     CUDA float32 field u0 [Ny, Nx]; returns u^nt (a new tensor unless `out`).
-    time_block: steps per launch (0: as many as the tile halo allows)."""
+    time_block: steps per launch (0: automatic, 1: one per launch, k: at most k)."""
     lib = _lib.load()
     u = _dev_f32(u0, "u0")
     if u.dim() != 2:

@@ -52,6 +52,8 @@ class GridDesc(ctypes.Structure):
         ("max_src", ctypes.c_int),
         ("max_rec", ctypes.c_int),
         ("zchunk", ctypes.c_int),
+        ("sinc_radius", ctypes.c_int),
+        ("sinc_beta", ctypes.c_double),
     ]
 
 

@@ -109,6 +109,9 @@ bool fdi_check_desc(const fd_grid_desc *d) {
     if (d->storage < 0 || d->storage > 2) return fdi_fail(FD_ERR_ARG, "storage"), false;
     if (d->amp_scale < 0.f || !std::isfinite(d->amp_scale)) return fdi_fail(FD_ERR_ARG, "amp_scale"), false;
     if (d->max_src < 0 || d->max_rec < 0 || d->zchunk < 0) return fdi_fail(FD_ERR_ARG, "capacities"), false;
+    if (d->sinc_radius < 0 || d->sinc_radius > kMaxSincR)
+        return fdi_fail(FD_ERR_ARG, "sinc_radius must be 0..%d", kMaxSincR), false;
+    if (!std::isfinite(d->sinc_beta)) return fdi_fail(FD_ERR_ARG, "sinc_beta"), false;
     long long pts = 1;
     for (int a = 0; a < d->ndim; ++a) pts *= (long long)d->shape[a] + 2LL * d->nbl;
     if (pts > (1LL << 34)) return fdi_fail(FD_ERR_ARG, "grid too large"), false;
@@ -161,21 +164,39 @@ struct WsPlan {
 
 constexpr int kNPart = 512;   // misfit partial sums
 
-size_t side_bytes(int cap, int nc, int nz, size_t off[6], size_t base) {
+size_t side_bytes(int cap, int nc, size_t nptr, size_t off[6], size_t base) {
     size_t o = base;
     off[0] = o; o = align_up(o + sizeof(long long) * (size_t)cap * nc, 256);
     off[1] = o; o = align_up(o + sizeof(float) * (size_t)cap * nc, 256);
-    off[2] = o; o = align_up(o + sizeof(int) * (size_t)(nz + 1), 256);
+    off[2] = o; o = align_up(o + sizeof(int) * nptr, 256);
     off[3] = o; o = align_up(o + sizeof(int4) * (size_t)cap * nc, 256);
     off[4] = o; o = align_up(o + sizeof(int) * (size_t)cap * nc, 256);
     off[5] = o; o = align_up(o + sizeof(float) * (size_t)cap * nc, 256);
     return o - base;
 }
 
+// Grid points one sparse point touches: the 2^d cell corners, or (2r)^d
+// windowed-sinc nodes.
+int sparse_nodes(const fd_grid_desc *d) {
+    if (d->sinc_radius == 0) return 1 << d->ndim;
+    int n = 1;
+    for (int a = 0; a < d->ndim; ++a) n *= 2 * d->sinc_radius;
+    return n;
+}
+
+// Tiles of the step kernels' xy (3D) or x (2D) decomposition; the injection
+// tables keep one plane-pointer row per tile.
+int xy_tiles(const Layout &L) {
+    const int ntx = (L.nx + kTileX - 1) / kTileX;
+    const int nty = L.ndim == 3 ? (L.ny + kTileY - 1) / kTileY : 1;
+    return ntx * nty;
+}
+
 WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     WsPlan w{};
     const size_t esz = d->storage == FD_STORE_F32 ? 4 : 2;
-    const int nc = 1 << d->ndim;
+    const int nc = sparse_nodes(d);
+    const size_t nptr = (size_t)xy_tiles(L) * (L.nz + 1);
     w.cap_src = d->max_src ? d->max_src : 64;
     w.cap_rec = d->max_rec ? d->max_rec : 4096;
     w.field_bytes = align_up((size_t)L.elems * esz, 256);
@@ -187,8 +208,8 @@ WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     w.uB = o; o += w.field_bytes;
     w.damp = o; o = align_up(o + sizeof(float) * (size_t)(L.nx + L.ny + L.nz), 256);
     w.misc = o; o = align_up(o + sizeof(double) * kNPart + 256, 256);
-    o += side_bytes(w.cap_src, nc, L.nz, w.src, o);
-    o += side_bytes(w.cap_rec, nc, L.nz, w.rec, o);
+    o += side_bytes(w.cap_src, nc, nptr, w.src, o);
+    o += side_bytes(w.cap_rec, nc, nptr, w.rec, o);
     w.total = o;
     // host staging mirrors the uploaded regions
     size_t s = 0;
@@ -297,10 +318,61 @@ int ensure_dt(fd_grid *g, double dt, hipStream_t s) {
     return FD_OK;
 }
 
-// Sparse tables of one side from host coordinates: multilinear weights of
-// the 2^d corners of the cell holding each point (cell N-2, fraction 1 for a
-// point on the last grid line), pitched offsets for sampling, and a per-plane
-// CSR of the distinct non-zero-weight corners for injection.
+constexpr double kPi = 3.14159265358979323846;
+
+// Modified Bessel function I0 by its power series sum_k ((x/2)^k / k!)^2
+// (all terms positive; x <= ~40 here).
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500 && term > 1e-18 * sum; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+    }
+    return sum;
+}
+
+// Interpolation weights of one point along one axis at fractional grid
+// position t (0 <= t <= n-1): multilinear (2 nodes, cell n-2 for a point on
+// the last line) or Kaiser-windowed sinc of half-width r (2r nodes from
+// floor(t) - r + 1; Hicks 2002).
+struct AxisWeights {
+    int k0, n;
+    double w[2 * kMaxSincR];
+};
+
+void axis_weights(double t, int n, int r, double beta, AxisWeights &o) {
+    if (r == 0) {
+        int k = (int)std::floor(t);
+        if (k >= n - 1) k = n - 2;
+        const double p = t - k;
+        o.k0 = k;
+        o.n = 2;
+        o.w[0] = 1.0 - p;
+        o.w[1] = p;
+        return;
+    }
+    const double b = beta > 0.0 ? beta : kPi * r / 2.0;
+    const double i0b = bessel_i0(b);
+    o.k0 = (int)std::floor(t) - r + 1;
+    o.n = 2 * r;
+    for (int i = 0; i < o.n; ++i) {
+        const double d = (double)(o.k0 + i) - t;   // signed distance in cells
+        double sinc;
+        if (d == std::round(d))
+            sinc = d == 0.0 ? 1.0 : 0.0;            // exact at the integers
+        else
+            sinc = std::sin(kPi * d) / (kPi * d);
+        const double u = 1.0 - (d / r) * (d / r);
+        o.w[i] = u >= 0.0 ? sinc * bessel_i0(b * std::sqrt(u)) / i0b : 0.0;
+    }
+}
+
+// Sparse tables of one side from host coordinates: the weights of the nodes
+// each point touches (tensor product of axis_weights; nodes outside the
+// padded grid dropped), pitched offsets for sampling (a dropped node points
+// at the zero column with weight 0), and the per-tile, per-plane CSR of the
+// distinct non-zero-weight nodes for injection.
 int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s) {
     const int ndim = g->d.ndim;
     const int cap = side == 0 ? g->wp.cap_src : g->wp.cap_rec;
@@ -314,72 +386,82 @@ int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s
 
     const Layout &L = g->L;
     const int nc = g->nc;
+    const int padded[3] = {L.nx, ndim == 3 ? L.ny : L.nz, L.nz};
+    const long long zcol = L.offset((L.nx + 3) & ~3, 0, 0);
     std::vector<long long> idx((size_t)npts * nc);
     std::vector<float> w((size_t)npts * nc);
-    struct Ent { int z, y, x, pt; float w; };
+    struct Ent { int tile, z, y, x, pt; float w; };
     std::vector<Ent> ents;
     ents.reserve((size_t)npts * nc);
+    AxisWeights aw[3];
     for (int p = 0; p < npts; ++p) {
-        int k[3] = {0, 0, 0};
-        double fr[3] = {0, 0, 0};
         for (int a = 0; a < ndim; ++a) {
             const double t = (xyz[(size_t)p * ndim + a] - g->d.origin[a]) / g->d.spacing[a];
             if (!(t >= 0.0 && t <= (double)(g->d.shape[a] - 1)))
                 return fdi_fail(FD_ERR_ARG, "%s %d outside the grid along axis %d",
                                 side ? "receiver" : "source", p, a);
-            int ki = (int)std::floor(t);
-            if (ki >= g->d.shape[a] - 1) ki = g->d.shape[a] - 2;
-            k[a] = ki;
-            fr[a] = t - ki;
+            axis_weights(t, g->d.shape[a], g->d.sinc_radius, g->d.sinc_beta, aw[a]);
         }
+        const int per = aw[0].n;   // nodes per axis
         for (int c = 0; c < nc; ++c) {
             int ix[3] = {0, 0, 0};
             double wt = 1.0;
+            bool inside = true;
+            int rem = c;
             for (int a = 0; a < ndim; ++a) {
-                const int b = (c >> a) & 1;
-                ix[a] = k[a] + b + g->d.nbl;
-                wt *= b ? fr[a] : 1.0 - fr[a];
+                const int k = rem % per;
+                rem /= per;
+                ix[a] = aw[a].k0 + k + g->d.nbl;
+                wt *= aw[a].w[k];
+                if (ix[a] < 0 || ix[a] >= padded[a]) inside = false;
+            }
+            const size_t slot = (size_t)p * nc + c;
+            if (!inside) {
+                idx[slot] = zcol;
+                w[slot] = 0.f;
+                continue;
             }
             int x = ix[0], y = 0, z = 0;
             if (ndim == 3) { y = ix[1]; z = ix[2]; } else { z = ix[1]; }
-            idx[(size_t)p * nc + c] = L.offset(x, y, z);
-            w[(size_t)p * nc + c] = (float)wt;
-            if (wt != 0.0) ents.push_back({z, y, x, p, (float)wt});
+            idx[slot] = L.offset(x, y, z);
+            w[slot] = (float)wt;
+            const int tile = (ndim == 3 ? (y / kTileY) * g->ntx : 0) + x / kTileX;
+            if ((float)wt != 0.f) ents.push_back({tile, z, y, x, p, (float)wt});
         }
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent &a, const Ent &b) {
+        if (a.tile != b.tile) return a.tile < b.tile;
         if (a.z != b.z) return a.z < b.z;
         if (a.y != b.y) return a.y < b.y;
         if (a.x != b.x) return a.x < b.x;
         return a.pt < b.pt;
     });
+    // distinct grid points (corners) and their contributing entries
     std::vector<int4> corners;
+    std::vector<long long> ckey;   // tile * (nz + 1) + z of each corner
     std::vector<int> esrc;
     std::vector<float> ew;
     for (size_t i = 0; i < ents.size();) {
         size_t j = i;
         const int beg = (int)esrc.size();
-        while (j < ents.size() && ents[j].z == ents[i].z && ents[j].y == ents[i].y && ents[j].x == ents[i].x) {
+        while (j < ents.size() && ents[j].tile == ents[i].tile && ents[j].z == ents[i].z &&
+               ents[j].y == ents[i].y && ents[j].x == ents[i].x) {
             esrc.push_back(ents[j].pt);
             ew.push_back(ents[j].w);
             ++j;
         }
         corners.push_back(make_int4(ents[i].x, ents[i].y, beg, (int)esrc.size()));
+        ckey.push_back((long long)ents[i].tile * (L.nz + 1) + ents[i].z);
         i = j;
     }
-    std::vector<int> pptr(L.nz + 1, 0);
-    // plane of each corner: recover from the sorted entries
+    // plane pointers of every tile: pptr[k] = first corner with key >= k
+    const size_t nptr = (size_t)g->ntx * g->nty * (L.nz + 1);
+    std::vector<int> pptr(nptr, 0);
     {
-        std::vector<int> cplane(corners.size());
-        size_t e = 0;
-        for (size_t c = 0; c < corners.size(); ++c) {
-            cplane[c] = ents[e].z;
-            e += (size_t)(corners[c].w - corners[c].z);
-        }
         size_t c = 0;
-        for (int z = 0; z <= L.nz; ++z) {
-            while (c < corners.size() && cplane[c] < z) ++c;
-            pptr[z] = (int)c;
+        for (size_t k = 0; k < nptr; ++k) {
+            while (c < ckey.size() && ckey[c] < (long long)k) ++c;
+            pptr[k] = (int)c;
         }
     }
 
@@ -396,8 +478,12 @@ int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s
         memcpy(st + (off[4] - base), esrc.data(), sizeof(int) * esrc.size());
         memcpy(st + (off[5] - base), ew.data(), sizeof(float) * ew.size());
     }
-    const size_t bytes = side == 0 ? g->wp.stage_side_bytes_src : g->wp.stage_side_bytes_rec;
-    HIPCHK(hipMemcpyAsync(g->ws + base, st, bytes, hipMemcpyHostToDevice, s));
+    // upload the used part of each table (the capacities can be large for
+    // windowed-sinc points)
+    const size_t used[6] = {sizeof(long long) * idx.size(), sizeof(float) * w.size(), sizeof(int) * pptr.size(),
+                            sizeof(int4) * corners.size(), sizeof(int) * esrc.size(), sizeof(float) * ew.size()};
+    for (int k = 0; k < 6; ++k)
+        if (used[k]) HIPCHK(hipMemcpyAsync(g->ws + off[k], st + (off[k] - base), used[k], hipMemcpyHostToDevice, s));
     rc = stage_release(g, s);
     if (rc) return rc;
     g->cached_xyz[side] = std::move(key);
@@ -447,6 +533,8 @@ Sample make_sample(const fd_grid *g, int side, int npts, float *out, float scale
     Sample s{};
     s.npts = npts;
     s.nc = g->nc;
+    s.lpp = 1;
+    while (s.lpp < g->nc && s.lpp < 64) s.lpp *= 2;
     s.idx = d.idx;
     s.w = d.w;
     s.out = out;
@@ -454,7 +542,7 @@ Sample make_sample(const fd_grid *g, int side, int npts, float *out, float scale
     return s;
 }
 
-inline int samp_blocks(const Sample &s) { return s.out ? (s.npts + kBlock - 1) / kBlock : 0; }
+inline int samp_blocks(const Sample &s) { return sample_blocks(s); }
 
 int check_dt(const fd_grid *g, double dt, int nt) {
     if (nt < 0) return fdi_fail(FD_ERR_ARG, "nt < 0");
@@ -505,7 +593,7 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     g->st = (Store)desc->storage;
     g->amp = (desc->storage != FD_STORE_F32 && desc->amp_scale > 0.f) ? desc->amp_scale : 1.f;
     g->auto_amp = desc->storage == FD_STORE_F16 && !(desc->amp_scale > 0.f);
-    g->nc = 1 << desc->ndim;
+    g->nc = sparse_nodes(desc);
     second_derivative_weights(L.r, g->c);
     g->cell = 1.0;
     for (int a = 0; a < desc->ndim; ++a) g->cell *= desc->spacing[a];
@@ -561,14 +649,19 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
         }
         int zc = desc->zchunk;
         if (zc <= 0) {
-            // One round of workgroups: as many z chunks per xy tile as the
-            // device holds resident step workgroups (occupancy x CUs), so no
-            // second, partly filled round of chunks trails the first.
+            // One balanced round of workgroups: z chunks per xy tile such
+            // that k workgroups run on every CU (at most what the kernel's
+            // occupancy allows), so no second, partly filled round trails
+            // the first.  Measured on 336^3, so 4..16: k = 2 is best for
+            // float32 fields, k = 3 for 16-bit ones (more concurrent columns
+            // thrash the per-XCD L2 that serves the halo reads; with half the
+            // bytes per point, 16-bit columns fit one more).
             int cus = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
                 cus <= 0)
                 cus = 256;
-            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m));
+            const int kmax = g->st == Store::F32 ? 2 : 3;
+            const int occ = std::max(1, std::min(kmax, step_blocks_per_cu(3, L.r, g->st, m)));
             const int tiles = g->ntx * g->nty;
             const int nzc = std::max(1, std::min(L.nz, occ * cus / std::max(1, tiles)));
             zc = (L.nz + nzc - 1) / nzc;

@@ -9,6 +9,7 @@
 namespace fd {
 
 constexpr int kMaxR = 8;          // space order 16
+constexpr int kMaxSincR = 8;      // windowed-sinc half-width of sparse points
 constexpr int kXOff = 64;         // elements before x = 0 in every row (>= kMaxR, 128-B aligned)
 constexpr int kTileX = 64;        // x points per tile (16 lanes x 4 points)
 constexpr int kTileY = 16;        // y rows per 3D tile (one row per 16 lanes)
@@ -36,27 +37,40 @@ struct Layout {
     }
 };
 
-// Per-plane CSR of the grid points that receive a point-source term in a
-// step.  Corner k lies at (x, y) of plane z with plane_ptr[z] <= k <
-// plane_ptr[z+1]; its value is sum_{e = beg..end-1} w[e] * vals[src[e]].
+// Per-tile, per-plane CSR of the grid points that receive a point-source
+// term in a step.  The tiles are those of the step kernels (64 x 16 in xy for
+// 3D, 64 in x for 2D), numbered tile = ty * ntx + tx.  Corner k lies at
+// (x, y) of plane z inside tile t with
+//   plane_ptr[t * (nz + 1) + z] <= k < plane_ptr[t * (nz + 1) + z + 1];
+// each grid point appears at most once, and its value is
+// sum_{e = beg..end-1} w[e] * vals[src[e]].
 struct Inject {
-    const int *plane_ptr;   // [nz + 1]
+    const int *plane_ptr;   // [tiles][nz + 1]
     const int4 *corner;     // (x, y, beg, end)
     const int *src;         // entry -> index into vals
-    const float *w;         // entry -> multilinear weight
+    const float *w;         // entry -> interpolation weight
     const float *vals;      // this step's row of values, nullptr = no injection
     float scale;            // multiplies every value
 };
 
-// Sampling of the centre field at sparse points by extra workgroups.
+// Sampling of the centre field at sparse points by extra workgroups: `lpp`
+// lanes (a power of two, at most 64) share one point.
 struct Sample {
     int npts;
-    int nc;                 // corners per point (2^ndim)
+    int nc;                 // nodes per point (2^ndim corners or (2r)^ndim sinc nodes)
+    int lpp;                // lanes per point
     const long long *idx;   // [npts][nc] element offsets in the pitched layout
     const float *w;         // [npts][nc]
     float *out;             // row of npts outputs, nullptr = no sampling
     float scale;
 };
+
+// Workgroups that sample the points of `s` (0 when it samples nothing).
+inline int sample_blocks(const Sample &s) {
+    if (!s.out || s.npts <= 0) return 0;
+    const int per = kBlock / s.lpp;
+    return (s.npts + per - 1) / per;
+}
 
 // Gradient support (float32 storage).  A recompute step (kBracket) also
 // writes, for time n, the imaging bracket
@@ -85,7 +99,7 @@ struct StepArgs {
     float wz[kMaxR + 1];
     int ntx, nty, ntz;      // tiles per axis (ntz counts z chunks in 3D)
     int zchunk;             // planes per 3D workgroup
-    int nsamp_blocks;       // leading workgroups that sample instead of stepping
+    int nsamp_blocks;       // trailing workgroups that sample instead of stepping
     Inject inj;
     Sample smp;
     Imaging img;

@@ -118,25 +118,44 @@ __device__ inline int xcd_remap(int h, int G) {
 template <Store S>
 __device__ void sample_block(const Sample &s, const void *field, int blk) {
     using E = Elem<S>;
-    const int i = blk * kBlock + (int)threadIdx.x;
-    if (i >= s.npts) return;
+    // s.lpp lanes share a point: each sums a strided share of its nodes, then
+    // the group reduces with xor shuffles (fixed order: deterministic).
+    const int lane = (int)threadIdx.x;
+    const int i = blk * (kBlock / s.lpp) + lane / s.lpp;
+    const int sub = lane & (s.lpp - 1);
     const typename E::T *f = (const typename E::T *)field;
     float v = 0.f;
-    for (int c = 0; c < s.nc; ++c)
-        v += s.w[(long long)i * s.nc + c] * E::ld(f + s.idx[(long long)i * s.nc + c]);
-    s.out[i] = v * s.scale;
+    if (i < s.npts) {
+        const long long b = (long long)i * s.nc;
+        for (int c = sub; c < s.nc; c += s.lpp) v = __builtin_fmaf(s.w[b + c], E::ld(f + s.idx[b + c]), v);
+    }
+    for (int o = s.lpp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (i < s.npts && sub == 0) s.out[i] = v * s.scale;
 }
 
-// Source term of the points (x..x+3, y) from the corners [e0, e1) of one
-// plane (all lanes of the workgroup walk the same, usually empty, list).
-__device__ inline void gather_sources(const Inject &inj, int e0, int e1, int x, int y, float &s0,
-                                      float &s1, float &s2, float &s3) {
+// Source terms of one plane of a 3D tile: the tile's corners [e0, e1) of
+// the plane are spread over the workgroup; each lane sums the weighted
+// values of its corners into the tile-shaped LDS buffer (a grid point occurs
+// once per plane, so no two lanes write one cell).
+__device__ inline void scatter_sources(const Inject &inj, int e0, int e1, int x0, int y0, float *s_src) {
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
+        const int4 c = inj.corner[e];
+        float v = 0.f;
+        for (int k = c.z; k < c.w; ++k) v = __builtin_fmaf(inj.w[k], inj.vals[inj.src[k]], v);
+        s_src[(c.y - y0) * kTileX + (c.x - x0)] = v * inj.scale;
+    }
+}
+
+// Source term of the points (x..x+3) of one 2D row from the row's corners
+// [e0, e1) in the tile (the lanes of a row walk the same short list).
+__device__ inline void gather_sources(const Inject &inj, int e0, int e1, int x, float &s0, float &s1,
+                                      float &s2, float &s3) {
     for (int e = e0; e < e1; ++e) {
         const int4 c = inj.corner[e];
         const int d = c.x - x;
-        if (c.y == y && (unsigned)d < 4u) {
+        if ((unsigned)d < 4u) {
             float v = 0.f;
-            for (int k = c.z; k < c.w; ++k) v += inj.w[k] * inj.vals[inj.src[k]];
+            for (int k = c.z; k < c.w; ++k) v = __builtin_fmaf(inj.w[k], inj.vals[inj.src[k]], v);
             v *= inj.scale;
             s0 += d == 0 ? v : 0.f;
             s1 += d == 1 ? v : 0.f;
@@ -146,10 +165,26 @@ __device__ inline void gather_sources(const Inject &inj, int e0, int e1, int x, 
     }
 }
 
+// The update and the Laplacian are written with explicit fused multiply-adds
+// so that every kernel instantiation (plain, bracket, imaging; any storage)
+// rounds them identically: a state recomputed by one step mode is bitwise
+// the state another mode computed, which checkpoint recomputation relies on.
 __device__ inline float update_point(float c, float m, float p, float lap, float src, float s) {
     const float alpha = (s == 0.f) ? 1.f : __builtin_amdgcn_rcpf(1.f + s);
     const float beta = 1.f - s;
-    return alpha * (2.f * c - beta * m + p * (lap + src));
+    const float t = __builtin_fmaf(-beta, m, 2.f * c);
+    return alpha * __builtin_fmaf(p, lap + src, t);
+}
+
+// One radius-j term of the Laplacian at a point: the weights times the sums
+// of the two neighbours at distance j along each axis (lap_term2: 2D).
+__device__ inline float lap_term3(float wx, float xs, float wy, float ys, float wz, float zs) {
+    float acc = wx * xs;
+    acc = __builtin_fmaf(wy, ys, acc);
+    return __builtin_fmaf(wz, zs, acc);
+}
+__device__ inline float lap_term2(float wx, float xs, float wz, float zs) {
+    return __builtin_fmaf(wz, zs, wx * xs);
 }
 
 // grad -= lam * br for the lane's 4 points (float64 accumulator; measured
@@ -182,7 +217,7 @@ __device__ inline void grad_epilogue(const Imaging &img, long long off, int nval
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float u1 = un[i], u0 = comp(c, i), um = comp(m, i);
-            b[i] = (u1 - 2.f * u0 + um) + s[i] * (u1 - um);
+            b[i] = __builtin_fmaf(s[i], u1 - um, (u1 - 2.f * u0) + um);
         }
         if (nvalid >= 4) {
             st4nt_f32(img.br_out + off, make_float4(b[0], b[1], b[2], b[3]));
@@ -207,12 +242,15 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     __shared__ float4 lds[2][LH * W4];
 
     const Layout L = a.L;
-    const int logical = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    if (logical < a.nsamp_blocks) {
-        sample_block<S>(a.smp, a.u, logical);
+    // Tile workgroups come first in dispatch order (renumbered per XCD); the
+    // sampling workgroups trail them and take free slots, so they never
+    // displace a tile into a second round.
+    const int ntile = (int)gridDim.x - a.nsamp_blocks;
+    if ((int)blockIdx.x >= ntile) {
+        sample_block<S>(a.smp, a.u, (int)blockIdx.x - ntile);
         return;
     }
-    int t = logical - a.nsamp_blocks;
+    int t = xcd_remap((int)blockIdx.x, ntile);
     const int bx = t % a.ntx;
     t /= a.ntx;
     const int by = t % a.nty;
@@ -227,10 +265,15 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     // a vector-memory wait for one would also drain the prefetched planes.
     __shared__ float s_dz[kMaxChunk];
     __shared__ int s_pp[kMaxChunk + 1];
+    const int *tile_pp = a.inj.plane_ptr + (long long)(by * a.ntx + bx) * (L.nz + 1);
     for (int i = lane; i <= z1 - z0; i += kBlock) {
         if (i < z1 - z0) s_dz[i] = a.damp[L.nx + L.ny + z0 + i];
-        s_pp[i] = a.inj.vals ? a.inj.plane_ptr[z0 + i] : 0;
+        s_pp[i] = a.inj.vals ? tile_pp[z0 + i] : 0;
     }
+    // Source terms of the current plane, scattered by the workgroup (one
+    // float4 per lane; a lane clears its cells after reading them).
+    __shared__ float4 s_src4[kTileY * kTileX / 4];
+    s_src4[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     const int tx = lane & 15, ty = lane >> 4;
     const int x = x0 + 4 * tx, y = y0 + ty;
     const bool active = (y < L.ny) && (x < L.nx);
@@ -337,7 +380,17 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             }
         }
         issue(ahead, z + 2);
+        // tables in LDS are block-uniform: the branches below are uniform
+        const int e0 = __builtin_amdgcn_readfirstlane(s_pp[z - z0]);
+        const int e1 = __builtin_amdgcn_readfirstlane(s_pp[z - z0 + 1]);
+        if (e0 < e1) scatter_sources(a.inj, e0, e1, x0, y0, reinterpret_cast<float *>(s_src4));
         __syncthreads();
+        float4 src4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e0 < e1) {
+            src4 = s_src4[lane];
+            s_src4[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            __syncthreads();   // cleared before any lane scatters the next plane
+        }
 
         if (active) {
             // x neighbours: 2*HX4+1 float4 chunks of the lane's LDS row
@@ -353,22 +406,19 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             }
             float lap[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) lap[i] = a.w0 * xs[4 * HX4 + i];
-#pragma unroll
             for (int j = 1; j <= R; ++j) {
                 const float4 yp = row[j * W4], ym = row[-j * W4];
                 const float4 zp = q[R + j], zm = q[R - j];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    float acc = a.wx[j] * (xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j]);
-                    acc += a.wy[j] * (comp(yp, i) + comp(ym, i));
-                    acc += a.wz[j] * (comp(zp, i) + comp(zm, i));
-                    lap[i] += acc;
+                    const float t = lap_term3(a.wx[j], xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j], a.wy[j],
+                                              comp(yp, i) + comp(ym, i), a.wz[j], comp(zp, i) + comp(zm, i));
+                    lap[i] = j == 1 ? t : lap[i] + t;
                 }
             }
-            float src[4] = {0.f, 0.f, 0.f, 0.f};
-            const int e0 = s_pp[z - z0], e1 = s_pp[z - z0 + 1];
-            if (e0 < e1) gather_sources(a.inj, e0, e1, x, y, src[0], src[1], src[2], src[3]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lap[i] = __builtin_fmaf(a.w0, xs[4 * HX4 + i], lap[i]);
+            const float src[4] = {src4.x, src4.y, src4.z, src4.w};
             const float sz = s_dz[z - z0];
             float un[4];
 #pragma unroll
@@ -377,6 +427,11 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
                                      sxy[i] + sz);
             const long long off = base + (long long)z * plane;
             const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
+            // All four results are computed here, before the ragged-edge
+            // branch: otherwise the compiler sinks the fourth point's
+            // Laplacian into the full-width store path and re-reads its LDS
+            // neighbours one at a time there, serialising LDS latency.
+            asm volatile("" ::"v"(r4.x), "v"(r4.y), "v"(r4.z), "v"(r4.w));
             const int nvalid = L.nx - x;
             if (nvalid >= 4) {
                 E::st4nt(O + off, r4);
@@ -398,6 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         for (int k = 0; k < 2 * R; ++k) q[k] = q[k + 1];
     };
 
+    __syncthreads();   // staged tables and the cleared source tile, before the first plane
     PlaneRegs s0, s1, s2;
     issue(s0, z0);
     issue(s1, z0 + 1);
@@ -424,21 +480,22 @@ __global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
     __shared__ float4 lds[LH * W4];
 
     const Layout L = a.L;
-    const int logical = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    if (logical < a.nsamp_blocks) {
-        sample_block<S>(a.smp, a.u, logical);
+    const int ntile = (int)gridDim.x - a.nsamp_blocks;   // tiles first, then sampling
+    if ((int)blockIdx.x >= ntile) {
+        sample_block<S>(a.smp, a.u, (int)blockIdx.x - ntile);
         return;
     }
-    const int t = logical - a.nsamp_blocks;
+    const int t = xcd_remap((int)blockIdx.x, ntile);
     const int bx = t % a.ntx, bz = t / a.ntx;
     const int x0 = bx * kTileX, z0 = bz * kTile2Z;
     const int z1 = min(z0 + kTile2Z, L.nz);
     const int lane = (int)threadIdx.x;
     __shared__ float s_dz[kTile2Z];
     __shared__ int s_pp[kTile2Z + 1];
+    const int *tile_pp = a.inj.plane_ptr + (long long)bx * (L.nz + 1);
     for (int i = lane; i <= z1 - z0; i += kBlock) {
         if (i < z1 - z0) s_dz[i] = a.damp[L.nx + L.ny + z0 + i];
-        s_pp[i] = a.inj.vals ? a.inj.plane_ptr[z0 + i] : 0;
+        s_pp[i] = a.inj.vals ? tile_pp[z0 + i] : 0;
     }
     const T *U = (const T *)a.u;
     const long long zcol = L.offset((L.nx + 3) & ~3, 0, 0);   // zero in every row
@@ -476,20 +533,20 @@ __global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
         }
         float lap[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lap[i] = a.w0 * xs[4 * HX4 + i];
-#pragma unroll
         for (int j = 1; j <= R; ++j) {
             const float4 zp = row[j * W4], zm = row[-j * W4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float acc = a.wx[j] * (xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j]);
-                acc += a.wz[j] * (comp(zp, i) + comp(zm, i));
-                lap[i] += acc;
+                const float t = lap_term2(a.wx[j], xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j], a.wz[j],
+                                          comp(zp, i) + comp(zm, i));
+                lap[i] = j == 1 ? t : lap[i] + t;
             }
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lap[i] = __builtin_fmaf(a.w0, xs[4 * HX4 + i], lap[i]);
         float src[4] = {0.f, 0.f, 0.f, 0.f};
         const int e0 = s_pp[z - z0], e1 = s_pp[z - z0 + 1];
-        if (e0 < e1) gather_sources(a.inj, e0, e1, x, 0, src[0], src[1], src[2], src[3]);
+        if (e0 < e1) gather_sources(a.inj, e0, e1, x, src[0], src[1], src[2], src[3]);
         const long long off = L.offset(x, 0, z);
         const float4 pc = ld4nt_f32(a.p + off);
         const float4 mc = E::ld4nt(Pv + off);
@@ -913,7 +970,7 @@ int step_blocks_per_cu(int ndim, int r, Store st, int mode) {
 
 hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s) {
     if (!smp.out || smp.npts <= 0) return hipSuccess;
-    const int blocks = (smp.npts + kBlock - 1) / kBlock;
+    const int blocks = sample_blocks(smp);
     switch (st) {
         case Store::F32: hipLaunchKernelGGL(k_sample<Store::F32>, dim3(blocks), dim3(kBlock), 0, s, smp, field); break;
         case Store::F16: hipLaunchKernelGGL(k_sample<Store::F16>, dim3(blocks), dim3(kBlock), 0, s, smp, field); break;

@@ -49,12 +49,13 @@ def oracle_forward(c, keep_history=False, u0=None, u_prev=None):
     vp = oracle.pad_velocity(g, c["v"])
     sig = oracle.damping(g, oracle.sigma_max_default(g, float(vp.max())))
     return oracle.forward(g, vp, sig, c["dt"], c["nt"], c["src"], c["wav"].astype(np.float64), c["rec"],
-                          u0=u0, u_prev=u_prev, keep_history=keep_history)
+                          u0=u0, u_prev=u_prev, keep_history=keep_history, sinc_radius=c.get("sinc", 0))
 
 
 def gpu_grid(c, **kw):
     from paper_1906_10811_amd import Grid
     dev = torch.device("cuda:0")
+    kw.setdefault("sinc_radius", c.get("sinc", 0))
     return Grid(c["shape"], c["spacing"], torch.from_numpy(c["v"]).to(dev), space_order=c["so"],
                 nbl=c["nbl"], origin=c["origin"], **kw)
 

@@ -22,11 +22,11 @@ def _hat(nx, ny, seed):
 
 
 @pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 16])
-@pytest.mark.parametrize("time_block", [0, 1, 3])
+@pytest.mark.parametrize("time_block", [0, 1, 3, 16])
 def test_diffusion_parity(so, time_block):
-    """203 x 141 (ragged 64 x 64 tiles), 121 steps: one step per launch, 3
-    per launch, or as many as the tile halo allows (16 / (so/2), with a
-    shorter last launch)."""
+    """203 x 141 (ragged 64 x 64 tiles), 121 steps: the automatic choice, one
+    step per launch, 3 per launch, or as many as the tile halo allows
+    (16 / (so/2), with a shorter last launch)."""
     need_gpu()
     from paper_1906_10811_amd import diffusion
     nx, ny, h = 203, 141, (1.0 / 202, 1.0 / 140)
@@ -42,8 +42,12 @@ def test_diffusion_parity(so, time_block):
     assert e <= 1e-5
 
 
+_FULL_WANT = {}   # oracle result of the current size, shared by both launch forms
+
+
+@pytest.mark.parametrize("time_block", [1, 16])
 @pytest.mark.parametrize("n", [2500, 10000])
-def test_diffusion_full_size(n):
+def test_diffusion_full_size(n, time_block):
     need_gpu()
     from paper_1906_10811_amd import diffusion
     so = 8
@@ -53,12 +57,14 @@ def test_diffusion_full_size(n):
     dt = 0.8 * oracle.diffusion_critical_dt(g, nu)
     u0 = _hat(n, n, 3).astype(np.float32)
     nt = 5
-    got = diffusion(torch.from_numpy(u0).cuda(), h, so, nu, dt, nt)
+    got = diffusion(torch.from_numpy(u0).cuda(), h, so, nu, dt, nt, time_block=time_block)
     torch.cuda.synchronize()
     got = got.cpu().numpy()
-    want = oracle.diffusion(g, u0.astype(np.float64), nu, dt, nt)
-    e = rel_l2(got, want)
-    print("diffusion %d^2 so 8, %d steps: rel L2 %.3e" % (n, nt, e))
+    if n not in _FULL_WANT:
+        _FULL_WANT.clear()
+        _FULL_WANT[n] = oracle.diffusion(g, u0.astype(np.float64), nu, dt, nt)
+    e = rel_l2(got, _FULL_WANT[n])
+    print("diffusion %d^2 so 8, %d steps, time_block %d: rel L2 %.3e" % (n, nt, time_block, e))
     assert e <= 1e-5
 
 
