@@ -159,7 +159,8 @@ def bench_cpu_baseline(w):
 
 def bench_gradient(torch, dev, stream):
     """fd_gradient on gradient3d_200: forward with checkpoints every 50 steps,
-    residual and FP64 misfit, segment recompute, adjoint with fused imaging."""
+    residual and FP64 misfit, segment recompute, adjoint with fused imaging;
+    then the binomial checkpoint schedule with 16 and 4 snapshot slots."""
     from paper_1906_10811_amd import Grid
     w = synth.workload("gradient3d_200")
     v_true = synth.velocity(w)
@@ -184,14 +185,42 @@ def bench_gradient(torch, dev, stream):
     torch.cuda.synchronize()
     secs = e0.elapsed_time(e1) / 1000.0 / reps
     # algorithmic bytes per point and time step: forward 16, recompute 16 +
-    # bracket write 4, adjoint 16 + bracket read 4 + FP64 accumulate 16, and
-    # two field copies (read + write) per checkpoint and per segment restore
+    # bracket write 4, adjoint 16 + bracket read 4 + float32 partial-sum
+    # read-modify-write 8, the fold into the float64 gradient (read 4, RMW 16,
+    # clear 4) every 32 adjoint steps, and two field copies (read + write)
+    # per checkpoint and per segment restore
     K = w["checkpoint_every"]
-    b_alg = 72.0 + 32.0 / K
+    b_alg = 64.0 + 24.0 / 32 + 32.0 / K
     gpts = g.padded_points * w["nt"] / secs / 1e9
     out = dict(workload="gradient3d_200", gpts=gpts, ms=secs * 1000.0, misfit=float(mis.item()),
                checkpoint_every=K, b_alg_per_pt=b_alg, achieved_gbs=gpts * b_alg,
-               frac_hbm=gpts * b_alg / HBM_PEAK_GBS)
+               frac_hbm=gpts * b_alg / HBM_PEAK_GBS,
+               workspace_gb=g.gradient_workspace_bytes(w["nt"], len(w["rec"]), checkpoint_every=K) / 1e9)
+    # binomial (revolve-optimal) schedules: fewer stored states, more
+    # recomputation.  Bytes per point: 16 per forward advance, 20 per
+    # bracket step and 28 + 24/32 per adjoint step (one each per time step),
+    # 16 per snapshot store or restore (two fields read and written).
+    from paper_1906_10811_amd._lib import FD_ACT_RESTORE, FD_ACT_STORE, checkpoint_schedule
+    nt = w["nt"]
+    out["binomial"] = {}
+    for slots in (16, 4):
+        acts, fwd = checkpoint_schedule(nt, slots)
+        copies = sum(1 for a in acts if a[0] in (FD_ACT_STORE, FD_ACT_RESTORE))
+        with torch.cuda.stream(stream):
+            g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], binomial_slots=slots, stream=stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            misb, _, _, _ = g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], binomial_slots=slots, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        sb = e0.elapsed_time(e1) / 1000.0
+        bytes_pt = (16.0 * fwd + (48.0 + 24.0 / 32) * nt + 16.0 * copies) / nt
+        gb = g.padded_points * nt / sb / 1e9
+        out["binomial"]["slots%d" % slots] = dict(
+            ms=sb * 1000.0, gpts=gb, forward_advances=fwd, recompute_factor=fwd / nt,
+            b_alg_per_pt=bytes_pt, frac_hbm=gb * bytes_pt / HBM_PEAK_GBS,
+            misfit_equal=bool(float(misb.item()) == float(mis.item())),
+            workspace_gb=g.gradient_workspace_bytes(nt, len(w["rec"]), binomial_slots=slots) / 1e9)
     g.close()
     return out
 
@@ -303,21 +332,22 @@ def bench_diffusion(torch, dev, stream):
             torch.cuda.synchronize()
             secs = e0.elapsed_time(e1) / 1000.0
             gpts = n * n * 1000 / secs / 1e9
-            # temporally blocked: 16/r steps per launch, 8 B per point per launch
-            lev = 16 // r
-            diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream, time_block=lev)
+            # the library's automatic choice: temporally blocked (8 B per point
+            # per launch of lev steps) at so 2 and 4, one step per launch above
+            lev = {1: 8, 2: 4}.get(r, 1)
+            diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream, time_block=0)
             torch.cuda.synchronize()
             with torch.cuda.stream(stream):
                 e0.record(stream)
-                diffusion(u0, (h, h), so, 0.5, dt, 1000, out=res, stream=stream, time_block=lev)
+                diffusion(u0, (h, h), so, 0.5, dt, 1000, out=res, stream=stream, time_block=0)
                 e1.record(stream)
             torch.cuda.synchronize()
             secs_tb = e0.elapsed_time(e1) / 1000.0
             gpts_tb = n * n * 1000 / secs_tb / 1e9
             out["%d^2 so%d" % (n, so)] = dict(
                 gpts=round(gpts, 1), frac_hbm=round(gpts * 8.0 / HBM_PEAK_GBS, 4),
-                blocked_gpts=round(gpts_tb, 1), steps_per_launch=lev,
-                blocked_frac_hbm=round(gpts_tb * 8.0 / lev / HBM_PEAK_GBS, 4))
+                auto_gpts=round(gpts_tb, 1), auto_steps_per_launch=lev,
+                auto_frac_hbm=round(gpts_tb * 8.0 / lev / HBM_PEAK_GBS, 4))
         del u0, res
     return out
 

@@ -172,6 +172,16 @@ class Grid:
                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
+    def gradient_workspace_bytes(self, nt: int, nrec: int, checkpoint_every: int = 50,
+                                 binomial_slots: int | None = None) -> int:
+        """fd_gradient_workspace_bytes for the schedule gradient() would use."""
+        flags, K = 0, int(checkpoint_every)
+        if binomial_slots is not None:
+            flags, K = _lib.FD_GRAD_BINOMIAL, int(binomial_slots)
+        n = ctypes.c_size_t()
+        _lib.check(_lib.load().fd_gradient_workspace_bytes(self._h, int(nt), int(nrec), K, flags, ctypes.byref(n)))
+        return n.value
+
     def gradient(self, src_xyz, wavelet: torch.Tensor, rec_xyz, d_obs: torch.Tensor, dt: float,
                  checkpoint_every: int = 50, residual_given: bool = False, want_src_adj: bool = False,
                  binomial_slots: int | None = None, stream=None):

@@ -163,6 +163,7 @@ struct WsPlan {
 };
 
 constexpr int kNPart = 512;   // misfit partial sums
+constexpr int kFoldEvery = 32;   // adjoint steps per float32 partial gradient sum
 
 size_t side_bytes(int cap, int nc, size_t nptr, size_t off[6], size_t base) {
     size_t o = base;
@@ -872,9 +873,10 @@ namespace {
 // the two rotating fields of the segment recompute and K imaging brackets.
 // Binomial (K = number of snapshot slots): K+1 snapshot pairs, the state
 // pair, the output field of the bracket step and one bracket.  Both: the
-// float64 accumulator (pitched), traces and residual.
+// float64 accumulator and the float32 partial sum (pitched), traces and
+// residual.
 struct GradPlan {
-    size_t ckpt, rot, br, grad, rec, resid, total;
+    size_t ckpt, rot, br, grad, gpart, rec, resid, total;
     int ncp, K, nbr;
     bool binomial;
 };
@@ -890,6 +892,7 @@ GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K, int flags) {
     p.rot = o; o += fb * 2;
     p.br = o; o += fb * (size_t)p.nbr;
     p.grad = o; o = align_up(o + sizeof(double) * (size_t)g->L.elems, 256);
+    p.gpart = o; o = align_up(o + sizeof(float) * (size_t)g->L.elems, 256);
     p.rec = o; o = align_up(o + sizeof(float) * (size_t)nt * nrec, 256);
     p.resid = o; o = align_up(o + sizeof(float) * (size_t)nt * nrec, 256);
     p.total = o;
@@ -940,6 +943,7 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     std::vector<float *> br(gp.nbr);
     for (int i = 0; i < gp.nbr; ++i) br[i] = (float *)(ws + gp.br + fb * (size_t)i);
     double *gacc = (double *)(ws + gp.grad);
+    float *gpart = (float *)(ws + gp.gpart);
     float *recb = (float *)(ws + gp.rec);
     float *resid = (float *)(ws + gp.resid);
     const long long nres = (long long)nt * sh->nrec;
@@ -966,7 +970,11 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
         return FD_OK;
     };
     // adjoint step k: lambda^{k-1} from lambda^k, lambda^{k+1}, residual row
-    // k-1, and grad -= lambda^{k-1} * bracket of level k-1
+    // k-1, and grad -= lambda^{k-1} * bracket of level k-1.  The products
+    // are summed in float32 and folded into the float64 gradient after every
+    // kFoldEvery adjoint steps of the reverse sweep (the same steps for every
+    // schedule, so the result does not depend on the schedule).
+    int adj_done = 0;
     auto adjoint_step = [&](int k, const float *brf) -> int {
         a.u = LA;
         a.prev = LB;
@@ -977,14 +985,16 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
         a.nsamp_blocks = samp_blocks(a.smp);
         a.img = Imaging{};
         a.img.br_in = brf;
-        a.img.grad = gacc;
+        a.img.gpart = gpart;
         a.ntz = g->ntz[kImage];
         a.zchunk = g->zchunk[kImage];
         HIPCHK(launch_step(a, g->st, kImage, s));
         std::swap(LA, LB);
+        if (++adj_done % kFoldEvery == 0) HIPCHK(launch_fold_f64(gacc, gpart, L.elems, s));
         return FD_OK;
     };
     HIPCHK(launch_zero_f64(gacc, L.elems, s));
+    HIPCHK(launch_zero_field(L, gpart, Store::F32, s));
 
     if (!gp.binomial) {
         // 1. forward with checkpoints of (u^c, u^{c-1}) every K steps
@@ -1075,6 +1085,7 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
             }
         }
     }
+    if (adj_done % kFoldEvery) HIPCHK(launch_fold_f64(gacc, gpart, L.elems, s));
     HIPCHK(launch_field_to_dense_f64(L, gacc, grad_m, s));
     if (src_adj) {
         Sample sm = make_sample(g, 0, sh->nsrc, src_adj, adj_smp);

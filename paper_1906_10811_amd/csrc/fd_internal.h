@@ -81,7 +81,7 @@ inline int sample_blocks(const Sample &s) {
 struct Imaging {
     float *br_out;          // kBracket: bracket of the step's time level
     const float *br_in;     // kImage: bracket of the step's time level
-    double *grad;           // kImage: float64 accumulator
+    float *gpart;           // kImage: float32 partial sum, folded into float64 by the host loop
 };
 
 enum StepMode { kPlain = 0, kBracket = 1, kImage = 2 };
@@ -133,6 +133,8 @@ hipError_t launch_diffuse2d_tb(const Layout &L, const float *u, float *out, floa
 hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
                          float *resid, double *partials, int npart, double *out, hipStream_t s);
 hipError_t launch_zero_f64(double *p, long long n, hipStream_t s);
+// acc[i] += part[i]; part[i] = 0 for i < n (n a multiple of 4, 16-B aligned)
+hipError_t launch_fold_f64(double *acc, float *part, long long n, hipStream_t s);
 hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, double *dense, hipStream_t s);
 
 }  // namespace fd

@@ -187,23 +187,21 @@ __device__ inline float lap_term2(float wx, float xs, float wz, float zs) {
     return __builtin_fmaf(wz, zs, wx * xs);
 }
 
-// grad -= lam * br for the lane's 4 points (float64 accumulator; measured
-// fastest with plain loads and stores issued after the update).
-__device__ inline void image_accumulate(double *g, int nvalid, const float un[4], const float4 &br) {
+// g -= lam * br for the lane's 4 points, into the float32 partial sum (the
+// host folds it into the float64 gradient every few adjoint steps).
+__device__ inline void image_accumulate(float *g, int nvalid, const float un[4], const float4 &br) {
     if (nvalid >= 4) {
-        double2 g0 = *reinterpret_cast<const double2 *>(g);
-        double2 g1 = *reinterpret_cast<const double2 *>(g + 2);
-        g0.x -= (double)un[0] * (double)br.x;
-        g0.y -= (double)un[1] * (double)br.y;
-        g1.x -= (double)un[2] * (double)br.z;
-        g1.y -= (double)un[3] * (double)br.w;
-        *reinterpret_cast<double2 *>(g) = g0;
-        *reinterpret_cast<double2 *>(g + 2) = g1;
+        float4 v = *reinterpret_cast<const float4 *>(g);
+        v.x = __builtin_fmaf(-un[0], br.x, v.x);
+        v.y = __builtin_fmaf(-un[1], br.y, v.y);
+        v.z = __builtin_fmaf(-un[2], br.z, v.z);
+        v.w = __builtin_fmaf(-un[3], br.w, v.w);
+        *reinterpret_cast<float4 *>(g) = v;
     } else {
         const float b[3] = {br.x, br.y, br.z};
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            if (i < nvalid) g[i] -= (double)un[i] * (double)b[i];
+            if (i < nvalid) g[i] = __builtin_fmaf(-un[i], b[i], g[i]);
     }
 }
 
@@ -227,7 +225,7 @@ __device__ inline void grad_epilogue(const Imaging &img, long long off, int nval
                 if (i < nvalid) img.br_out[off + i] = b[i];
         }
     } else if constexpr (MODE == kImage) {
-        image_accumulate(img.grad + off, nvalid, un, ld4nt_f32(img.br_in + off));
+        image_accumulate(img.gpart + off, nvalid, un, ld4nt_f32(img.br_in + off));
     }
 }
 
@@ -446,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
                 for (int i = 0; i < 4; ++i) sv[i] = sxy[i] + sz;
                 grad_epilogue<MODE>(a.img, off, nvalid, un, q[R], cur.mv, sv);
             } else if constexpr (MODE == kImage) {
-                image_accumulate(a.img.grad + off, nvalid, un, ld4nt_f32(a.img.br_in + off));
+                image_accumulate(a.img.gpart + off, nvalid, un, ld4nt_f32(a.img.br_in + off));
             }
         }
 #pragma unroll
@@ -1004,6 +1002,28 @@ hipError_t launch_zero_field(const Layout &L, void *f, Store st, hipStream_t s) 
         hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(L.elems)), dim3(kBlock), 0, s, (float *)f, L.elems);
     else
         hipLaunchKernelGGL(k_zero<uint16_t>, dim3(grid_for(L.elems)), dim3(kBlock), 0, s, (uint16_t *)f, L.elems);
+    return hipGetLastError();
+}
+
+__global__ void k_fold_f64(double *acc, float *part, long long n4) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float4 p = reinterpret_cast<const float4 *>(part)[i];
+        double2 *a = reinterpret_cast<double2 *>(acc) + 2 * i;
+        double2 a0 = a[0], a1 = a[1];
+        a0.x += p.x;
+        a0.y += p.y;
+        a1.x += p.z;
+        a1.y += p.w;
+        a[0] = a0;
+        a[1] = a1;
+        reinterpret_cast<float4 *>(part)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+hipError_t launch_fold_f64(double *acc, float *part, long long n, hipStream_t s) {
+    if (n % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fold_f64, dim3(grid_for(n / 4)), dim3(kBlock), 0, s, acc, part, n / 4);
     return hipGetLastError();
 }
 
