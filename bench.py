@@ -196,6 +196,23 @@ def bench_gradient(torch, dev, stream):
                checkpoint_every=K, b_alg_per_pt=b_alg, achieved_gbs=gpts * b_alg,
                frac_hbm=gpts * b_alg / HBM_PEAK_GBS,
                workspace_gb=g.gradient_workspace_bytes(w["nt"], len(w["rec"]), checkpoint_every=K) / 1e9)
+    # every bracket resident (checkpoint_every >= nt: 800 FP32 fields of 280^3
+    # fit in HBM): the forward pass writes the brackets, nothing is
+    # recomputed; bytes per point and step 20 + 28 + 24/32
+    with torch.cuda.stream(stream):
+        g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], checkpoint_every=w["nt"], stream=stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        misa, _, _, _ = g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], checkpoint_every=w["nt"], stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    sa = e0.elapsed_time(e1) / 1000.0
+    ga = g.padded_points * w["nt"] / sa / 1e9
+    ba = 48.0 + 24.0 / 32
+    out["all_brackets_resident"] = dict(
+        ms=sa * 1000.0, gpts=ga, b_alg_per_pt=ba, frac_hbm=ga * ba / HBM_PEAK_GBS,
+        misfit_equal=bool(float(misa.item()) == float(mis.item())),
+        workspace_gb=g.gradient_workspace_bytes(w["nt"], len(w["rec"]), checkpoint_every=w["nt"]) / 1e9)
     # binomial (revolve-optimal) schedules: fewer stored states, more
     # recomputation.  Bytes per point: 16 per forward advance, 20 per
     # bracket step and 28 + 24/32 per adjoint step (one each per time step),
@@ -253,7 +270,9 @@ def bench_sinc(torch, dev, stream):
     for r in (4, 8):
         g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], sinc_radius=r, stream=stream)
         secs, _ = time_forward(torch, g, w, wav, 1, 1, stream)
-        res["r%d" % r] = dict(gpts=round(g.padded_points * w["nt"] / secs / 1e9, 1), nodes_per_point=(2 * r) ** 3)
+        gp = g.padded_points * w["nt"] / secs / 1e9
+        res["r%d" % r] = dict(gpts=round(gp, 1), nodes_per_point=(2 * r) ** 3, b_alg_per_pt=B_STEP,
+                              frac_hbm=round(gp * B_STEP / HBM_PEAK_GBS, 4))
         g.close()
     return res
 
@@ -349,6 +368,18 @@ def bench_diffusion(torch, dev, stream):
                 auto_gpts=round(gpts_tb, 1), auto_steps_per_launch=lev,
                 auto_frac_hbm=round(gpts_tb * 8.0 / lev / HBM_PEAK_GBS, 4))
         del u0, res
+    # the FP64 oracle on the host, a few steps of the 2500^2 so-8 case
+    import oracle
+    n, so, steps = 2500, 8, 3
+    h = 1.0 / (n - 1)
+    og = oracle.Grid((n, n), (h, h), (0.0, 0.0), so)
+    dt = 0.8 * oracle.diffusion_critical_dt(og, 0.5)
+    u = np.ones((n, n))
+    t0 = time.perf_counter()
+    oracle.diffusion(og, u, 0.5, dt, steps)
+    secs = time.perf_counter() - t0
+    out["oracle_2500^2_so8"] = dict(gpts=round(n * n * steps / secs / 1e9, 4), steps=steps, seconds=round(secs, 2),
+                                    kind="oracle (numpy, FP64)")
     return out
 
 

@@ -175,8 +175,10 @@ int fd_adjoint(fd_grid *grid, const fd_shot *shot, int nt, double dt,
 
 /* Device workspace for fd_gradient.  Default: checkpoints of (u^c, u^{c-1})
  * every checkpoint_every steps and checkpoint_every bracket fields of the
- * segment recompute.  FD_GRAD_BINOMIAL: checkpoint_every + 1 snapshots and
- * two scratch fields.  Both add the float64 accumulator, traces and
+ * segment recompute; with checkpoint_every >= nt, nt bracket fields and no
+ * checkpoint (the forward pass keeps every bracket, nothing is recomputed).
+ * FD_GRAD_BINOMIAL: checkpoint_every + 1 snapshots and two scratch fields.
+ * All add the float64 gradient, its float32 partial sum, traces and
  * residual. */
 int fd_gradient_workspace_bytes(const fd_grid *grid, int nt, int nrec,
                                 int checkpoint_every, int flags, size_t *bytes);
@@ -213,8 +215,11 @@ int fd_checkpoint_schedule(int nt, int slots, fd_ckpt_action *actions, int capac
  * checkpointing modes give bitwise the same result):
  *   J = 1/2 sum_n sum_r (rec_r[n] - d_obs_r[n])^2
  *   g_m = - sum_n lambda^n [(u^{n+1} - 2u^n + u^{n-1}) + (sigma dt/2)(u^{n+1} - u^{n-1})]
- * with lambda the adjoint field driven by the residual.  Forward wavefields
- * are recomputed from checkpoints.  d_obs_dev: device float32 [nt][nrec]
+ * with lambda the adjoint field driven by the residual.  The bracket of each
+ * level comes from a forward step that also writes it: recomputed from
+ * checkpoints, or kept from the forward pass when checkpoint_every >= nt.
+ * Products are summed in float32 over 32 adjoint steps, then added to the
+ * float64 gradient.  d_obs_dev: device float32 [nt][nrec]
  * (the residual itself when flags has FD_GRAD_RESIDUAL_GIVEN).
  * misfit_dev: device double[1]; grad_m_dev: device double, dense padded;
  * rec_out (nullable): device float32 [nt][nrec]; src_adj (nullable): device

@@ -884,7 +884,7 @@ GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K, int flags) {
     GradPlan p{};
     p.K = K;
     p.binomial = (flags & FD_GRAD_BINOMIAL) != 0;
-    p.ncp = p.binomial ? std::min(K, nt) + 1 : (nt + K - 1) / K;
+    p.ncp = p.binomial ? std::min(K, nt) + 1 : (K >= nt ? 0 : (nt + K - 1) / K);
     p.nbr = p.binomial ? 2 : std::min(K, nt);   // binomial: output field + bracket
     const size_t fb = g->wp.field_bytes;
     size_t o = 0;
@@ -996,7 +996,26 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     HIPCHK(launch_zero_f64(gacc, L.elems, s));
     HIPCHK(launch_zero_field(L, gpart, Store::F32, s));
 
-    if (!gp.binomial) {
+    if (!gp.binomial && K >= nt) {
+        // Every bracket fits the workspace: the forward pass itself writes
+        // the bracket of each level (no checkpoint, no recompute), then the
+        // residual, then the whole adjoint sweep.
+        void *A = rotA, *B = rotB;   // u^n, u^{n-1}
+        HIPCHK(launch_zero_field(L, A, g->st, s));
+        HIPCHK(launch_zero_field(L, B, g->st, s));
+        for (int n = 0; n < nt; ++n) {
+            if ((rc = bracket_step(n, A, B, B, br[n], n >= 1 ? recb + (size_t)(n - 1) * sh->nrec : nullptr)))
+                return rc;
+            std::swap(A, B);
+        }
+        Sample sm = make_sample(g, 1, sh->nrec, recb + (size_t)(nt - 1) * sh->nrec, 1.f);
+        HIPCHK(launch_sample(sm, A, g->st, s));
+        HIPCHK(launch_misfit(recb, d_obs, nres, given, resid, g->partials, kNPart, misfit, s));
+        HIPCHK(launch_zero_field(L, g->uA, g->st, s));
+        HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+        for (int k = nt; k >= 1; --k)
+            if ((rc = adjoint_step(k, br[k - 1]))) return rc;
+    } else if (!gp.binomial) {
         // 1. forward with checkpoints of (u^c, u^{c-1}) every K steps
         HIPCHK(launch_zero_field(L, g->uA, g->st, s));
         HIPCHK(launch_zero_field(L, g->uB, g->st, s));

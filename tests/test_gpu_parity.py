@@ -187,6 +187,22 @@ def test_gradient_parity(K):
     assert eg <= 1e-4
 
 
+def test_gradient_resident_brackets_equal_recompute():
+    """checkpoint_every >= nt keeps every bracket from the forward pass (no
+    recompute); the result is bitwise the recomputing schedule's."""
+    need_gpu()
+    c, vp, sig, d_obs = _gradient_case()
+    g = gpu_grid(c)
+    dev = torch.device("cuda:0")
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    obs = torch.from_numpy(d_obs).to(dev)
+    m1, g1, r1, a1 = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=13, want_src_adj=True)
+    m2, g2, r2, a2 = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=c["nt"], want_src_adj=True)
+    torch.cuda.synchronize()
+    _print("resident brackets", grad_bitwise=int(torch.equal(g1, g2)), traces_bitwise=int(torch.equal(r1, r2)))
+    assert torch.equal(r1, r2) and torch.equal(m1, m2) and torch.equal(g1, g2) and torch.equal(a1, a2)
+
+
 @pytest.mark.parametrize("slots", [0, 3, 9])
 def test_gradient_binomial_schedule(slots):
     """The binomial checkpoint schedule (snapshot slots 0, 3, 9) reproduces
