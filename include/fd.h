@@ -272,7 +272,10 @@ int fd_server_create(const fd_server_desc *desc, fd_server **out);
 /* Copy the request's host inputs and queue it; returns at once. */
 int fd_submit(fd_server *srv, const fd_request *req, uint64_t *ticket);
 /* Block until the ticket completes or timeout_s passes (FD_ERR_TIMEOUT);
- * timeout_s < 0 waits forever.  A completed ticket can be waited once. */
+ * timeout_s < 0 waits forever.  A completed ticket is collected once: a
+ * second wait, or a wait on a ticket never issued, returns FD_ERR_ARG (a
+ * concurrent waiter that loses the race gets FD_ERR_STATE).  A failed
+ * request returns its status with the worker's message in fd_last_error. */
 int fd_wait(fd_server *srv, uint64_t ticket, double timeout_s, fd_result *result);
 /* Bytes of the request's reservation (what admission charges against the budget). */
 int fd_request_bytes(const fd_request *req, size_t *bytes);

@@ -327,7 +327,7 @@ class Server:
         rc = _lib.load().fd_wait(self._h, ctypes.c_uint64(ticket), float(timeout), ctypes.byref(res))
         if rc == _lib.FD_ERR_TIMEOUT:
             raise TimeoutError("ticket %d" % ticket)
-        keep = self._keep.pop(ticket)
+        keep = self._keep.pop(ticket, None)
         _lib.check(rc)
         return keep[4], {"status": res.status, "t_submit": res.t_submit, "t_start": res.t_start,
                          "t_done": res.t_done, "bytes": res.bytes_reserved}

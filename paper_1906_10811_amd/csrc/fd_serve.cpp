@@ -22,6 +22,8 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -111,6 +113,7 @@ struct Req {
     hipEvent_t ev = nullptr;
     bool ev_pending = false;
     fd_result res{};
+    std::string msg;   // error message of a failed request
 };
 
 }  // namespace
@@ -127,6 +130,7 @@ struct fd_server {
     std::deque<Req *> pending;
     std::vector<Req *> active;
     std::map<uint64_t, Req *> done;
+    std::set<uint64_t> live;   // tickets submitted and not yet collected by fd_wait
     bool stopping = false;
     uint64_t next_ticket = 1;
     size_t peak_bytes = 0;
@@ -162,6 +166,7 @@ int fd_server::admit(Req *r) {
 }
 
 void fd_server::finish(Req *r, int status) {
+    if (status != FD_OK) r->msg = fd_last_error();
     if (r->grid && status == FD_OK) {
         hipStream_t s = streams[r->slot];
         if (hipMemcpyAsync(r->rec_out_host, r->d_rec, sizeof(float) * (size_t)r->nt * r->nrec,
@@ -391,6 +396,7 @@ extern "C" int fd_submit(fd_server *srv, const fd_request *req, uint64_t *ticket
         }
         r->ticket = srv->next_ticket++;
         r->res.t_submit = srv->now();
+        srv->live.insert(r->ticket);
         srv->pending.push_back(r);
         *ticket = r->ticket;
         srv->cv_work.notify_one();
@@ -405,19 +411,28 @@ extern "C" int fd_submit(fd_server *srv, const fd_request *req, uint64_t *ticket
 extern "C" int fd_wait(fd_server *srv, uint64_t ticket, double timeout_s, fd_result *result) {
     if (!srv) return fdi_fail(FD_ERR_ARG, "null server");
     std::unique_lock<std::mutex> lk(srv->mu);
-    if (ticket == 0 || ticket >= srv->next_ticket) return fdi_fail(FD_ERR_ARG, "unknown ticket");
-    auto ready = [&] { return srv->done.count(ticket) > 0; };
+    if (!srv->live.count(ticket))
+        return fdi_fail(FD_ERR_ARG, "unknown or already collected ticket %llu", (unsigned long long)ticket);
+    // done, or collected meanwhile by another waiter of the same ticket
+    auto ready = [&] { return srv->done.count(ticket) > 0 || !srv->live.count(ticket); };
     if (timeout_s < 0) {
         srv->cv_done.wait(lk, ready);
     } else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
         return fdi_fail(FD_ERR_TIMEOUT, "ticket %llu not done", (unsigned long long)ticket);
     }
-    Req *r = srv->done[ticket];
-    srv->done.erase(ticket);
+    auto it = srv->done.find(ticket);
+    if (it == srv->done.end())
+        return fdi_fail(FD_ERR_STATE, "ticket %llu collected by another waiter", (unsigned long long)ticket);
+    Req *r = it->second;
+    srv->done.erase(it);
+    srv->live.erase(ticket);
+    srv->cv_done.notify_all();
     if (result) *result = r->res;
     const int st = r->res.status;
+    const std::string msg = r->msg;
     delete r;
-    return st == FD_OK ? FD_OK : fdi_fail(st, "request %llu failed", (unsigned long long)ticket);
+    return st == FD_OK ? FD_OK
+                       : fdi_fail(st, "request %llu failed: %s", (unsigned long long)ticket, msg.c_str());
 }
 
 extern "C" int fd_server_stats(fd_server *srv, size_t *peak_bytes, int *peak_slots) {

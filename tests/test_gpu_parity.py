@@ -187,6 +187,31 @@ def test_gradient_parity(K):
     assert eg <= 1e-4
 
 
+@pytest.mark.parametrize("K", [9, 1000])
+def test_gradient_parity_2d(K):
+    """The 2D kernel's bracket and imaging epilogues: fd_gradient on a 2D
+    damped case vs the oracle (ragged segments, and every bracket kept)."""
+    need_gpu()
+    c = case((61, 47), 8, 5, 180, seed=12, nsrc=1, nrec=9)
+    og = c["og"]
+    vp = oracle.pad_velocity(og, c["v"])
+    sig = oracle.damping(og, oracle.sigma_max_default(og, float(vp.max())))
+    v_true = vp.copy()
+    v_true[15:35, 20:45] *= 1.1
+    wav = c["wav"].astype(np.float64)
+    d_obs, *_ = oracle.forward(og, v_true, sig, c["dt"], c["nt"], c["src"], wav, c["rec"])
+    J, grad, _ = oracle.gradient(og, vp, sig, c["dt"], c["nt"], c["src"], wav, c["rec"], d_obs)
+    g = gpu_grid(c)
+    dev = torch.device("cuda:0")
+    mis, gm, _, _ = g.gradient(c["src"], torch.from_numpy(c["wav"]).to(dev), c["rec"],
+                               torch.from_numpy(d_obs.astype(np.float32)).to(dev), c["dt"], checkpoint_every=K)
+    torch.cuda.synchronize()
+    eJ = abs(float(mis.item()) - J) / J
+    eg = rel_l2(gm.cpu().numpy(), grad)
+    _print("gradient 2d K=%d" % K, J=J, eJ=eJ, grad=eg)
+    assert eJ <= 1e-4 and eg <= 1e-4
+
+
 def test_gradient_resident_brackets_equal_recompute():
     """checkpoint_every >= nt keeps every bracket from the forward pass (no
     recompute); the result is bitwise the recomputing schedule's."""

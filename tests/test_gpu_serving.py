@@ -104,3 +104,19 @@ def test_oversized_request_rejected_and_others_complete():
         out, info = srv.wait(t, timeout=120.0)
         assert info["status"] == 0 and np.isfinite(out).all() and np.abs(out).max() > 0
     srv.close()
+
+
+def test_ticket_is_collected_once():
+    """A second wait on a collected ticket, and a wait on a ticket never
+    issued, are rejected instead of blocking."""
+    need_gpu()
+    from paper_1906_10811_amd import FDError, Server
+    r = _requests(1, seed=13)[0]
+    srv = Server(1 << 30, max_slots=1)
+    t = srv.submit(**r)
+    srv.wait(t, timeout=120.0)
+    for bad in (t, t + 1000):
+        with pytest.raises(FDError) as e:
+            srv.wait(bad, timeout=5.0)
+        assert e.value.code == -1
+    srv.close()
