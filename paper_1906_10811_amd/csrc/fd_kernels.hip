@@ -187,21 +187,23 @@ __device__ inline float lap_term2(float wx, float xs, float wz, float zs) {
     return __builtin_fmaf(wz, zs, wx * xs);
 }
 
-// g -= lam * br for the lane's 4 points, into the float32 partial sum (the
-// host folds it into the float64 gradient every few adjoint steps).
-__device__ inline void image_accumulate(float *g, int nvalid, const float un[4], const float4 &br) {
+// g -= lam * br for the lane's 4 points into the float32 partial sum (the
+// host folds it into the float64 gradient every few adjoint steps); gv is
+// the partial sum's current value at those points.
+__device__ inline void image_accumulate(float *g, int nvalid, const float un[4], const float4 &br,
+                                        const float4 &gv) {
+    float4 v;
+    v.x = __builtin_fmaf(-un[0], br.x, gv.x);
+    v.y = __builtin_fmaf(-un[1], br.y, gv.y);
+    v.z = __builtin_fmaf(-un[2], br.z, gv.z);
+    v.w = __builtin_fmaf(-un[3], br.w, gv.w);
     if (nvalid >= 4) {
-        float4 v = *reinterpret_cast<const float4 *>(g);
-        v.x = __builtin_fmaf(-un[0], br.x, v.x);
-        v.y = __builtin_fmaf(-un[1], br.y, v.y);
-        v.z = __builtin_fmaf(-un[2], br.z, v.z);
-        v.w = __builtin_fmaf(-un[3], br.w, v.w);
-        *reinterpret_cast<float4 *>(g) = v;
+        st4nt_f32(g, v);
     } else {
-        const float b[3] = {br.x, br.y, br.z};
+        const float r[3] = {v.x, v.y, v.z};
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            if (i < nvalid) g[i] = __builtin_fmaf(-un[i], b[i], g[i]);
+            if (i < nvalid) g[i] = r[i];
     }
 }
 
@@ -225,7 +227,7 @@ __device__ inline void grad_epilogue(const Imaging &img, long long off, int nval
                 if (i < nvalid) img.br_out[off + i] = b[i];
         }
     } else if constexpr (MODE == kImage) {
-        image_accumulate(img.gpart + off, nvalid, un, ld4nt_f32(img.br_in + off));
+        image_accumulate(img.gpart + off, nvalid, un, ld4nt_f32(img.br_in + off), ld4nt_f32(img.gpart + off));
     }
 }
 
@@ -352,6 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     struct PlaneRegs {
         float4 front, pv, mv;
         float4 hv[HPT];   // halo of plane z+R
+        float4 br, gp;    // imaging step: bracket and partial gradient of plane z
     };
     auto issue = [&](PlaneRegs &r, int zz) {
         zz = min(zz, z1 - 1);   // past the chunk: a harmless in-bounds reload
@@ -361,6 +364,10 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4(U + hoff[k] + zo + (long long)R * plane);
         r.pv = ld4nt_f32(Pp + base + zo);
         r.mv = E::ld4nt(Pv + base + zo);
+        if constexpr (MODE == kImage) {
+            r.br = ld4nt_f32(a.img.br_in + base + zo);
+            r.gp = ld4nt_f32(a.img.gpart + base + zo);
+        }
     };
     auto body = [&](int z, const PlaneRegs &cur, PlaneRegs &ahead) {
         float4 *buf = lds[(z - z0) & 1];
@@ -444,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
                 for (int i = 0; i < 4; ++i) sv[i] = sxy[i] + sz;
                 grad_epilogue<MODE>(a.img, off, nvalid, un, q[R], cur.mv, sv);
             } else if constexpr (MODE == kImage) {
-                image_accumulate(a.img.gpart + off, nvalid, un, ld4nt_f32(a.img.br_in + off));
+                image_accumulate(a.img.gpart + off, nvalid, un, cur.br, cur.gp);
             }
         }
 #pragma unroll
