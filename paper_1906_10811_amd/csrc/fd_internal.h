@@ -76,8 +76,9 @@ inline int sample_blocks(const Sample &s) {
 // writes, for time n, the imaging bracket
 //   br^n = (u^{n+1} - 2 u^n + u^{n-1}) + s (u^{n+1} - u^{n-1}),  s = sigma dt/2,
 // from the three levels it holds in registers; an adjoint step (kImage)
-// then accumulates grad -= lam^n * br^n in float64 for its new value lam^n.
-// br and grad use the pitched field layout (grad in doubles).
+// then accumulates grad -= lam^n * br^n for its new value lam^n into a
+// float32 partial sum, which the host folds into the float64 gradient every
+// few steps.  br and the partial sum use the pitched field layout.
 struct Imaging {
     float *br_out;          // kBracket: bracket of the step's time level
     const float *br_in;     // kImage: bracket of the step's time level
