@@ -650,21 +650,34 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
         }
         int zc = desc->zchunk;
         if (zc <= 0) {
-            // One balanced round of workgroups: z chunks per xy tile such
-            // that k workgroups run on every CU (at most what the kernel's
-            // occupancy allows), so no second, partly filled round trails
-            // the first.  Measured on 336^3, so 4..16: k = 2 is best for
-            // float32 fields, k = 3 for 16-bit ones (more concurrent columns
-            // thrash the per-XCD L2 that serves the halo reads; with half the
-            // bytes per point, 16-bit columns fit one more).
+            // One balanced round of workgroups: k workgroups on every CU
+            // (2 <= k <= min(3, occupancy)), with the number of z chunks per
+            // xy tile that fills k * CUs slots best, so no second, partly
+            // filled round trails the first.  On a tie, k = 2 for float32
+            // fields and k = 3 for 16-bit ones: measured on 336^3, so 4..16,
+            // k = 2 wins by 0.5-5 % in float32 and k = 3 by 6-13 % in 16-bit
+            // (more concurrent columns thrash the per-XCD L2 that serves the
+            // halo reads; with half the bytes per point, 16-bit columns fit
+            // one more).  On 280^3 (90 tiles) the fill decides: k = 3 fills
+            // 94 % of the slots, k = 2 only 88 %.
             int cus = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
                 cus <= 0)
                 cus = 256;
-            const int kmax = g->st == Store::F32 ? 2 : 3;
-            const int occ = std::max(1, std::min(kmax, step_blocks_per_cu(3, L.r, g->st, m)));
-            const int tiles = g->ntx * g->nty;
-            const int nzc = std::max(1, std::min(L.nz, occ * cus / std::max(1, tiles)));
+            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m));
+            const int tiles = std::max(1, g->ntx * g->nty);
+            const int kmax = std::min(occ, 3), prefer = g->st == Store::F32 ? 2 : 3;
+            int nzc = 1;
+            double best = -1.0;
+            for (int k = std::min(2, kmax); k <= kmax; ++k) {
+                const int n = std::max(1, std::min(L.nz, k * cus / tiles));
+                const double fill = std::min(1.0, (double)n * tiles / ((double)k * cus));
+                const double score = fill - (k == prefer ? 0.0 : 0.02);
+                if (score > best) {
+                    best = score;
+                    nzc = n;
+                }
+            }
             zc = (L.nz + nzc - 1) / nzc;
             // Wide xy planes leave few chunks per round; long chunks then
             // lose more to the round tail than short ones lose to their
