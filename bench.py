@@ -352,8 +352,8 @@ def bench_diffusion(torch, dev, stream):
             secs = e0.elapsed_time(e1) / 1000.0
             gpts = n * n * 1000 / secs / 1e9
             # the library's automatic choice: temporally blocked (8 B per point
-            # per launch of lev steps) at so 2 and 4, one step per launch above
-            lev = {1: 8, 2: 4}.get(r, 1)
+            # per launch of lev steps) at so 2, 4 and 8, one step per launch otherwise
+            lev = {1: 8, 2: 8, 4: 4}.get(r, 1)
             diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream, time_block=0)
             torch.cuda.synchronize()
             with torch.cuda.stream(stream):

@@ -296,9 +296,9 @@ typedef struct fd_diffusion_desc {
     double spacing[2];     /* h_x, h_y > 0 */
     int space_order;       /* even, 2..16 */
     double nu;             /* diffusivity > 0 */
-    int time_block;        /* steps per launch: 0 = automatic (8 at so 2, 4 at
-                              so 4, where the LDS-blocked kernel beats one step
-                              per launch, else 1), 1 = one step per launch,
+    int time_block;        /* steps per launch: 0 = automatic (8 at so 2 and 4,
+                              4 at so 8, where the LDS-blocked kernel beats one
+                              step per launch, else 1), 1 = one step per launch,
                               k > 1 = at most min(k, 16 / (so/2)) */
 } fd_diffusion_desc;
 

@@ -95,12 +95,13 @@ extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, 
     // temporal blocking: each launch advances up to `per` levels from a tile
     // staged with an r*per halo (the thesis's OPS tiling / YASK wave-front
     // tiling idea, Section 2.2 and 2.3.1, in LDS)
-    // Automatic choice (measured on 2500^2 and 10000^2): 8 levels at radius
-    // 1 and 4 at radius 2 (staged halo 8, 16-byte aligned); at larger radii
-    // the redundant halo levels cost more than the HBM traffic they save.
+    // Automatic choice (measured on 2500^2 and 10000^2 for every radius and
+    // level count): 8 levels at radius 1 and 2, 4 at radius 4; at the other
+    // radii the redundant halo levels cost more than the HBM traffic they
+    // save, and one step per launch is faster.
     int per = diffuse2d_max_levels(L.r);
     if (desc->time_block > 0) per = std::min(per, desc->time_block);
-    else per = L.r == 1 ? 8 : L.r == 2 ? 4 : 1;
+    else per = (L.r == 1 || L.r == 2) ? 8 : L.r == 4 ? 4 : 1;
     for (int n = 0; n < nt;) {
         const int lev = std::min(per, nt - n);
         if (per <= 1)

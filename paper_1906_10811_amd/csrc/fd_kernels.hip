@@ -667,8 +667,7 @@ constexpr int kTbHalo = 16;                        // R * levels per launch, at 
 constexpr int kTbRows = kTile2Z + 2 * kTbHalo;     // 96 staged rows
 constexpr int kTbPadX = 4;                         // zero floats left/right of a staged row
 constexpr int kTbW4 = (kTileX + 2 * kTbHalo + 2 * kTbPadX) / 4;   // float4 per staged row
-constexpr int kTbGroups = (kTileX + 2 * kTbHalo) / 4 * kTbRows;   // 4-point groups of level 1 at most
-constexpr int kTbPerLane = (kTbGroups + kBlock - 1) / kBlock;
+constexpr int kTbPerLane = (kTbRows * kTbW4 + kBlock - 1) / kBlock;   // staged float4 groups per lane
 
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int nlev) {
@@ -679,7 +678,8 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int n
     const int H = R * nlev;                       // staged halo of this launch
     const int x0 = bx * kTileX - H, z0 = bz * kTile2Z - H;   // grid coords of staged (0, 0)
     const int rows = kTile2Z + 2 * H;
-    const int g4 = (kTileX + 2 * H) / 4 + 2;      // staged float4 per row incl. pads
+    const int g4 = kTbW4;                         // staged float4 per row: the full LDS row, so every
+                                                  // neighbour group a level reads holds grid data or zero
     const int lane = (int)threadIdx.x;
     // stage level 0; float4 column c covers grid x = x0 - 4 + 4c (a float4
     // load when that is 16-B aligned in the grid, else element by element)
@@ -704,29 +704,44 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int n
     }
     __syncthreads();
     const float *ldsf = reinterpret_cast<const float *>(lds);
+    // Each lane owns fixed float4 groups of the staged tile (row-major with
+    // the constant row stride, so the index split is a multiply-shift); a
+    // level updates the groups inside its exact region.  Neighbours are read
+    // as whole float4 groups: x from the 2 ceil(R/4) + 1 groups of the row,
+    // z from the groups j rows up and down (conflict-free 16-byte LDS reads).
+    constexpr int HX4 = (R + 3) / 4;
     for (int t = 1; t <= nlev; ++t) {
-        // level t region: rows [R t, rows - R t), floats [PadX + 4 floor(R t / 4), ...) in groups of 4
+        // level t region: rows [R t, rows - R t), float4 columns [c0, c1)
         const int r0 = R * t, r1 = rows - R * t;
         const int c0 = 1 + (R * t) / 4;                        // first float4 column (pad column is 0)
         const int c1 = 1 + (kTileX + 2 * H - R * t + 3) / 4;   // one past the last
-        const int ncol = c1 - c0, nrow = r1 - r0;
         float4 res[kTbPerLane];
 #pragma unroll
         for (int k = 0; k < kTbPerLane; ++k) {
             const int gidx = lane + k * kBlock;
+            const int lr = gidx / kTbW4, c = gidx - lr * kTbW4;
             res[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gidx < ncol * nrow) {
-                const int lr = r0 + gidx / ncol, c = c0 + gidx % ncol;
-                const float *rowp = ldsf + (lr * kTbW4 + c) * 4;   // first of the group's 4 floats
+            if (lr >= r0 && lr < r1 && c >= c0 && c < c1) {
+                const float4 *row = lds + lr * kTbW4 + c;
+                float xs[4 * (2 * HX4 + 1)];
+#pragma unroll
+                for (int q = -HX4; q <= HX4; ++q) {
+                    const float4 v = row[q];
+                    xs[4 * (q + HX4) + 0] = v.x;
+                    xs[4 * (q + HX4) + 1] = v.y;
+                    xs[4 * (q + HX4) + 2] = v.z;
+                    xs[4 * (q + HX4) + 3] = v.w;
+                }
                 float un[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) un[i] = a.w0 * rowp[i];
+                for (int i = 0; i < 4; ++i) un[i] = a.w0 * xs[4 * HX4 + i];
 #pragma unroll
                 for (int j = 1; j <= R; ++j) {
+                    const float4 zp = row[j * kTbW4], zm = row[-j * kTbW4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        float acc = a.wx[j] * (rowp[i + j] + rowp[i - j]);
-                        acc += a.wz[j] * (rowp[i + j * kTbW4 * 4] + rowp[i - j * kTbW4 * 4]);
+                        float acc = a.wx[j] * (xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j]);
+                        acc += a.wz[j] * (comp(zp, i) + comp(zm, i));
                         un[i] += acc;
                     }
                 }
@@ -736,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int n
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const bool in = gz >= 0 && gz < L.nz && gx + i >= 0 && gx + i < L.nx;
-                    o[i] = in ? un[i] + rowp[i] : 0.f;   // the field is zero outside the grid
+                    o[i] = in ? un[i] + xs[4 * HX4 + i] : 0.f;   // the field is zero outside the grid
                 }
                 res[k] = make_float4(o[0], o[1], o[2], o[3]);
             }
@@ -745,10 +760,8 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int n
 #pragma unroll
         for (int k = 0; k < kTbPerLane; ++k) {
             const int gidx = lane + k * kBlock;
-            if (gidx < ncol * nrow) {
-                const int lr = r0 + gidx / ncol, c = c0 + gidx % ncol;
-                lds[lr * kTbW4 + c] = res[k];
-            }
+            const int lr = gidx / kTbW4, c = gidx - lr * kTbW4;
+            if (lr >= r0 && lr < r1 && c >= c0 && c < c1) lds[lr * kTbW4 + c] = res[k];
         }
         __syncthreads();
     }
