@@ -168,3 +168,36 @@ def test_full_length_properties_layered3d_256():
     assert e_rec <= 1e-4
     assert dot <= 1e-6
     assert math.isfinite(a1) and a1 > 0
+
+
+@pytest.mark.slow
+def test_storage_error_growth_over_1500_steps():
+    """The precision form at the full step count of the 512^3 GRF workload,
+    on a 96^3 + 40 grid the oracle runs in under a minute: trace error
+    against the FP64 oracle over the first 500, 1000 and 1500 steps for each
+    storage type (float32 stays within the 1e-5 gate over the whole run)."""
+    need_gpu()
+    from paper_1906_10811_amd import Grid
+    shape, h, nbl, nt, so = (96, 96, 96), (10.0, 10.0, 10.0), 40, 1500, 8
+    v = synth.grf_model(shape, h, seed=1)
+    dt = 0.4 * 10.0 / synth.VMAX
+    src = [(475.0 + 5.0, 475.0 + 5.0, 20.0)]
+    rec = synth.line_receivers(96, 0.0, 950.0, (475.0, 20.0), 3)
+    wav = synth.ricker(nt, dt, 15.0).astype(np.float32)[:, None]
+    g0 = oracle.Grid(shape, h, (0.0, 0.0, 0.0), so, nbl)
+    vp = oracle.pad_velocity(g0, v)
+    sig = oracle.damping(g0, oracle.sigma_max_default(g0, float(vp.max())))
+    want, *_ = oracle.forward(g0, vp, sig, dt, nt, src, wav.astype(np.float64), rec)
+    dev = torch.device("cuda:0")
+    rows = {}
+    for st in ("f32", "f16", "bf16"):
+        g = Grid(shape, h, torch.from_numpy(v).to(dev), space_order=so, nbl=nbl, storage=st)
+        got = g.forward(src, torch.from_numpy(wav).to(dev), rec, dt)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        g.close()
+        rows[st] = [rel_l2(got[:n], want[:n]) for n in (500, 1000, 1500)]
+    print("trace error vs FP64 over 500/1000/1500 steps:",
+          {k: ["%.2e" % e for e in v] for k, v in rows.items()}, flush=True)
+    assert max(rows["f32"]) <= 1e-5
+    assert max(rows["f16"]) <= 5e-3 and max(rows["bf16"]) <= 5e-2
