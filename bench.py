@@ -215,14 +215,13 @@ def bench_gradient(torch, dev, stream):
         workspace_gb=g.gradient_workspace_bytes(w["nt"], len(w["rec"]), checkpoint_every=w["nt"]) / 1e9)
     # binomial (revolve-optimal) schedules: fewer stored states, more
     # recomputation.  Bytes per point: 16 per forward advance, 20 per
-    # bracket step and 28 + 24/32 per adjoint step (one each per time step),
-    # 16 per snapshot store or restore (two fields read and written).
-    from paper_1906_10811_amd._lib import FD_ACT_RESTORE, FD_ACT_STORE, checkpoint_schedule
+    # bracket step and 28 + 24/32 per adjoint step (one each per time step);
+    # snapshots are kept by reference, never copied.
+    from paper_1906_10811_amd._lib import checkpoint_schedule
     nt = w["nt"]
     out["binomial"] = {}
     for slots in (16, 4):
-        acts, fwd = checkpoint_schedule(nt, slots)
-        copies = sum(1 for a in acts if a[0] in (FD_ACT_STORE, FD_ACT_RESTORE))
+        _, fwd = checkpoint_schedule(nt, slots)
         with torch.cuda.stream(stream):
             g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], binomial_slots=slots, stream=stream)
             torch.cuda.synchronize()
@@ -231,7 +230,7 @@ def bench_gradient(torch, dev, stream):
             e1.record(stream)
         torch.cuda.synchronize()
         sb = e0.elapsed_time(e1) / 1000.0
-        bytes_pt = (16.0 * fwd + (48.0 + 24.0 / 32) * nt + 16.0 * copies) / nt
+        bytes_pt = (16.0 * fwd + (48.0 + 24.0 / 32) * nt) / nt
         gb = g.padded_points * nt / sb / 1e9
         out["binomial"]["slots%d" % slots] = dict(
             ms=sb * 1000.0, gpts=gb, forward_advances=fwd, recompute_factor=fwd / nt,

@@ -1054,39 +1054,67 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
                 if ((rc = adjoint_step(k, br[k - 1 - c]))) return rc;
         }
     } else {
-        // Binomial schedule: the state pair (A = u^n, B = u^{n-1}) moves by
-        // ADVANCE, is saved by STORE and reset by RESTORE; YOUTURN takes one
-        // bracket step out of place and the adjoint step that consumes it.
-        // The first sweep samples the receivers; the first YOUTURN (level
-        // nt-1) completes the traces and forms the residual.
-        void *A = rotA, *B = rotB;
+        // Binomial schedule over a pool of fields (the checkpoint pairs and
+        // the two rotating fields) with reference counts instead of copies:
+        // a snapshot slot references the two fields of the state it saved,
+        // RESTORE makes those fields the current state, and a step whose
+        // in-place target is referenced by a slot writes a free field
+        // instead.  The pool always holds one: the slots reference at most
+        // 2 (slots + 1) of its 2 (slots + 1) + 2 fields, and when a step needs
+        // a free field at most one of the current two is unreferenced.
+        // YOUTURN takes one bracket step out of place and the adjoint step
+        // that consumes it.  The first sweep samples the receivers; the first
+        // YOUTURN (level nt-1) completes the traces and forms the residual.
+        const int npool = 2 * gp.ncp + 2;
+        std::vector<void *> pool(npool);
+        for (int i = 0; i < 2 * gp.ncp; ++i) pool[i] = ck[i];
+        pool[2 * gp.ncp] = rotA;
+        pool[2 * gp.ncp + 1] = rotB;
+        std::vector<int> ref(npool, 0);
+        std::vector<int> slot_u(gp.ncp, -1), slot_p(gp.ncp, -1);
         float *out_f = br[0], *brf = br[1];
-        HIPCHK(launch_zero_field(L, A, g->st, s));
-        HIPCHK(launch_zero_field(L, B, g->st, s));
+        int cu = 0, cp = 1;   // pool fields of (u^n, u^{n-1})
+        // Every pool field is zeroed once: a step writes only the grid points
+        // of its output, so the zero halo that realises the zero extension
+        // must already be there in whichever field it writes.
+        for (int i = 0; i < npool; ++i) HIPCHK(launch_zero_field(L, pool[i], g->st, s));
         HIPCHK(launch_zero_field(L, g->uA, g->st, s));
         HIPCHK(launch_zero_field(L, g->uB, g->st, s));
-        HIPCHK(hipMemcpyAsync(ck[0], A, fb, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(ck[1], B, fb, hipMemcpyDeviceToDevice, s));
-        int cur = 0;   // level held by (A, B), -1 if it is not a stored one
+        slot_u[0] = cu;
+        slot_p[0] = cp;
+        ref[cu] = ref[cp] = 1;
+        auto free_field = [&]() -> int {
+            for (int i = 0; i < npool; ++i)
+                if (ref[i] == 0 && i != cu && i != cp) return i;
+            return -1;
+        };
         for (const fd_ckpt_action &act : plan) {
             switch (act.kind) {
-                case FD_ACT_STORE:
-                    HIPCHK(hipMemcpyAsync(ck[2 * act.slot], A, fb, hipMemcpyDeviceToDevice, s));
-                    HIPCHK(hipMemcpyAsync(ck[2 * act.slot + 1], B, fb, hipMemcpyDeviceToDevice, s));
-                    cur = act.step;
-                    break;
-                case FD_ACT_RESTORE:
-                    if (cur != act.step) {
-                        HIPCHK(hipMemcpyAsync(A, ck[2 * act.slot], fb, hipMemcpyDeviceToDevice, s));
-                        HIPCHK(hipMemcpyAsync(B, ck[2 * act.slot + 1], fb, hipMemcpyDeviceToDevice, s));
-                        cur = act.step;
+                case FD_ACT_STORE: {
+                    if (act.slot < 0 || act.slot >= gp.ncp) return fdi_fail(FD_ERR_STATE, "bad schedule slot");
+                    if (slot_u[act.slot] >= 0) {
+                        --ref[slot_u[act.slot]];
+                        --ref[slot_p[act.slot]];
                     }
+                    slot_u[act.slot] = cu;
+                    slot_p[act.slot] = cp;
+                    ++ref[cu];
+                    ++ref[cp];
+                    break;
+                }
+                case FD_ACT_RESTORE:
+                    if (act.slot < 0 || act.slot >= gp.ncp || slot_u[act.slot] < 0)
+                        return fdi_fail(FD_ERR_STATE, "bad schedule slot");
+                    cu = slot_u[act.slot];
+                    cp = slot_p[act.slot];
                     break;
                 case FD_ACT_ADVANCE:
                     for (int n = act.step; n < act.step + act.count; ++n) {
-                        a.u = A;
-                        a.prev = B;
-                        a.out = B;
+                        const int out = ref[cp] == 0 ? cp : free_field();
+                        if (out < 0) return fdi_fail(FD_ERR_STATE, "checkpoint pool exhausted");
+                        a.u = pool[cu];
+                        a.prev = pool[cp];
+                        a.out = pool[out];
                         a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, fwd_inj);
                         a.smp = make_sample(g, 1, sh->nrec,
                                             (act.first && n >= 1) ? recb + (size_t)(n - 1) * sh->nrec : nullptr, 1.f);
@@ -1095,13 +1123,13 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
                         a.ntz = g->ntz[kPlain];
                         a.zchunk = g->zchunk[kPlain];
                         HIPCHK(launch_step(a, g->st, kPlain, s));
-                        std::swap(A, B);
+                        cp = cu;
+                        cu = out;
                     }
-                    cur = -1;
                     break;
                 case FD_ACT_YOUTURN: {
                     const int n = act.step;
-                    if ((rc = bracket_step(n, A, B, out_f, brf,
+                    if ((rc = bracket_step(n, pool[cu], pool[cp], out_f, brf,
                                            (act.first && n >= 1) ? recb + (size_t)(n - 1) * sh->nrec : nullptr)))
                         return rc;
                     if (act.first) {   // n == nt-1: last trace row, then the residual
