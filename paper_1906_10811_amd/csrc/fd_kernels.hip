@@ -258,6 +258,13 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     const int x0 = bx * kTileX, y0 = by * kTileY;
     const int z0 = bz * a.zchunk;
     const int z1 = min(z0 + a.zchunk, L.nz);
+    // Odd chunks march downwards: two adjacent chunks then read the warm-up
+    // planes around their common boundary at about the same time (both at
+    // their start, or both at their end), while the first read is still
+    // cached.  Measured: 0.5 % fewer fetched bytes, 0.5-1 % faster.
+    const int dir = (bz & 1) ? -1 : 1;
+    const int len = z1 - z0;
+    const int zs = dir > 0 ? z0 : z1 - 1;   // first plane of the march
 
     const int lane = (int)threadIdx.x;
     // Per-plane tables of this chunk (damping along z, source CSR pointers)
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     }
     float4 q[2 * R + 1];
 #pragma unroll
-    for (int k = 0; k < 2 * R; ++k) q[k] = E::ld4(U + base + (long long)(z0 - R + k) * plane);
+    for (int k = 0; k < 2 * R; ++k) q[k] = E::ld4(U + base + (long long)(zs + dir * (k - R)) * plane);
 
     // Halo ring: each lane keeps the halo items it loads in R+1 LDS slots.
     // A halo row of plane z belongs to a neighbour tile, which streams plane
@@ -344,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int k = 0; k < HPT; ++k)
-            if (hl[k] >= 0) ring[i * NH + lane + k * kBlock] = E::ld4(U + hoff[k] + (long long)(z0 + i) * plane);
+            if (hl[k] >= 0) ring[i * NH + lane + k * kBlock] = E::ld4(U + hoff[k] + (long long)(zs + dir * i) * plane);
 
     // Loads for plane z: the queue front u(z+R), the halo of plane z+R,
     // dt^2 v^2 and u^{n-1}.  Three register sets rotate so that the loads of
@@ -356,12 +363,13 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         float4 hv[HPT];   // halo of plane z+R
         float4 br, gp;    // imaging step: bracket and partial gradient of plane z
     };
-    auto issue = [&](PlaneRegs &r, int zz) {
-        zz = min(zz, z1 - 1);   // past the chunk: a harmless in-bounds reload
-        const long long zo = (long long)zz * plane;
-        r.front = E::ld4(U + base + zo + (long long)R * plane);
+    auto issue = [&](PlaneRegs &r, int st) {
+        st = min(st, len - 1);   // past the chunk: a harmless in-bounds reload
+        const long long zo = (long long)(zs + dir * st) * plane;
+        const long long fo = zo + (long long)(dir * R) * plane;   // the queue front, R planes ahead
+        r.front = E::ld4(U + base + fo);
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4(U + hoff[k] + zo + (long long)R * plane);
+        for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4(U + hoff[k] + fo);
         r.pv = ld4nt_f32(Pp + base + zo);
         r.mv = E::ld4nt(Pv + base + zo);
         if constexpr (MODE == kImage) {
@@ -369,14 +377,15 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             r.gp = ld4nt_f32(a.img.gpart + base + zo);
         }
     };
-    auto body = [&](int z, const PlaneRegs &cur, PlaneRegs &ahead) {
-        float4 *buf = lds[(z - z0) & 1];
+    auto body = [&](int st, const PlaneRegs &cur, PlaneRegs &ahead) {
+        const int z = zs + dir * st;
+        float4 *buf = lds[st & 1];
         q[2 * R] = cur.front;
         buf[(R + ty) * W4 + HX4 + tx] = q[R];
         // park the halo of plane z+R (fetched with the front of the same
         // plane) and stage the halo of plane z parked R planes ago
-        float4 *ring_w = ring + ((z - z0 + R) % kRing) * NH + lane;
-        const float4 *ring_r = ring + ((z - z0) % kRing) * NH + lane;
+        float4 *ring_w = ring + ((st + R) % kRing) * NH + lane;
+        const float4 *ring_r = ring + (st % kRing) * NH + lane;
 #pragma unroll
         for (int k = 0; k < HPT; ++k) {
             if (hl[k] >= 0) {
@@ -384,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
                 buf[hl[k]] = ring_r[k * kBlock];
             }
         }
-        issue(ahead, z + 2);
+        issue(ahead, st + 2);
         // tables in LDS are block-uniform: the branches below are uniform
         const int e0 = __builtin_amdgcn_readfirstlane(s_pp[z - z0]);
         const int e1 = __builtin_amdgcn_readfirstlane(s_pp[z - z0 + 1]);
@@ -460,16 +469,16 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
 
     __syncthreads();   // staged tables and the cleared source tile, before the first plane
     PlaneRegs s0, s1, s2;
-    issue(s0, z0);
-    issue(s1, z0 + 1);
-    int z = z0;
-    for (; z + 3 <= z1; z += 3) {
-        body(z, s0, s2);
-        body(z + 1, s1, s0);
-        body(z + 2, s2, s1);
+    issue(s0, 0);
+    issue(s1, 1);
+    int st = 0;
+    for (; st + 3 <= len; st += 3) {
+        body(st, s0, s2);
+        body(st + 1, s1, s0);
+        body(st + 2, s2, s1);
     }
-    if (z < z1) body(z, s0, s2);
-    if (z + 1 < z1) body(z + 1, s1, s0);
+    if (st < len) body(st, s0, s2);
+    if (st + 1 < len) body(st + 1, s1, s0);
 }
 
 // ------------------------------------------------------------------ 2D step
