@@ -148,13 +148,20 @@ int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t ws_bytes,
  * Waits for the work last enqueued on the grid (its latest stream) first. */
 int fd_grid_destroy(fd_grid *grid);
 
+/* Fill *info with the facts above (host only; FD_ERR_ARG on a null argument). */
 int fd_grid_get_info(const fd_grid *grid, fd_grid_info *info);
 
 /*
- * Forward modelling: nt steps of the update from u^0, u^{-1} (zero unless
- * opts says otherwise) with dt (FD_ERR_UNSTABLE if dt >= critical_dt).
+ * Forward modelling: the Operator applied for nt time steps with step dt
+ * (Section 2.1.1; one launch per step from the host time loop, Section
+ * 3.3.2), from u^0, u^{-1} (zero unless opts says otherwise).
  * rec_out: device float32 [nt][nrec], row n = receivers sampling u^{n+1}.
- * opts may be NULL.
+ * opts may be NULL; nt = 0 only applies opts (state in, state out).
+ * Source and receiver tables are rebuilt on the host when the coordinates
+ * differ from the previous call's.  Errors: FD_ERR_UNSTABLE if dt >=
+ * critical_dt; FD_ERR_ARG for nt < 0, a null required pointer, a point
+ * outside the grid or more points than max_src / max_rec; FD_ERR_DEVICE if
+ * a HIP call fails.  A rejected call leaves the grid usable.
  */
 int fd_forward(fd_grid *grid, const fd_shot *shot, int nt, double dt,
                float *rec_out, const fd_fwd_opts *opts, void *stream);
@@ -163,7 +170,9 @@ int fd_forward(fd_grid *grid, const fd_shot *shot, int nt, double dt,
  * Adjoint modelling (the exact transpose of fd_forward for a fixed medium,
  * zero initial state): residual_dev [nt][nrec] device float32 is injected at
  * the receivers backwards in time; src_adj_dev [nt][nsrc] device float32
- * receives (F^T r)_s[n] = dt^2/prod(h) sum_c W_s,c lambda^n.
+ * receives (F^T r)_s[n] = dt^2/prod(h) sum_c W_s,c lambda^n.  The same step
+ * kernel runs with the roles of sources and receivers exchanged.  Errors as
+ * for fd_forward.
  */
 int fd_adjoint(fd_grid *grid, const fd_shot *shot, int nt, double dt,
                const float *residual_dev, float *src_adj_dev, void *stream);
@@ -247,7 +256,8 @@ typedef struct fd_server_desc {
 
 typedef struct fd_request {
     fd_grid_desc grid;         /* grid of this shot */
-    const float *vp_host;      /* host float32 velocity (copied at admission) */
+    const float *vp_host;      /* host float32 velocity, physical or padded per grid.vp_padded
+                                  (copied at submission) */
     int nsrc;
     const double *src_xyz;     /* host [nsrc][ndim] */
     const float *wavelet_host; /* host [nt][nsrc] (copied at submission) */
@@ -268,8 +278,12 @@ typedef struct fd_result {
 
 typedef struct fd_server fd_server;
 
+/* Create a server on desc->device: allocates the arena (one device
+ * allocation of hbm_budget_bytes) and max_slots non-blocking streams, and
+ * starts one scheduler thread.  FD_ERR_NOMEM if the arena cannot be had. */
 int fd_server_create(const fd_server_desc *desc, fd_server **out);
-/* Copy the request's host inputs and queue it; returns at once. */
+/* Copy the request's host inputs and queue it; returns at once.  A request
+ * larger than the whole budget completes with FD_ERR_NOMEM (at fd_wait). */
 int fd_submit(fd_server *srv, const fd_request *req, uint64_t *ticket);
 /* Block until the ticket completes or timeout_s passes (FD_ERR_TIMEOUT);
  * timeout_s < 0 waits forever.  A completed ticket is collected once: a
