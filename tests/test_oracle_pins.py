@@ -76,7 +76,7 @@ def test_weights_polynomial_order(so):
 # ---------------------------------------------------------- Laplacian (O4)
 def test_stencil_point_set_so2():
     """A unit impulse touches exactly the 5-point star printed for so 2 in
-    Section 3.3.3 (s2d_ut0_5pt)."""
+    Section 3.3.3."""
     gold = _golden("diffusion_so2_kernel.txt")
     want = {tuple(int(x) for x in p.split(",")) for p in gold["points"]}
     g = oracle.Grid((9, 9), (1.0, 1.0), (0.0, 0.0), 2)
@@ -601,33 +601,38 @@ def test_gradient_matches_finite_differences():
 
 
 # ---------------------------------------------------- 2D diffusion (Sec 5.1.2)
-def _printed_so2_kernel(u, dt, hx, hy, hoisted):
-    """The so-2 diffusion kernel as printed (Section 3.2.2 with divisions;
-    Section 5.1.5 with hoisted reciprocals), evaluated on interior points of
-    a zero-padded copy; axis 0 of the array is y, axis 1 is x."""
+def _so2_update_from_printed_values(u, dt, hx, hy, hoisted):
+    """One so-2 diffusion update built from the coefficients the thesis
+    prints (tests/golden: -1.0 on the centre, 0.5 on each +-1 neighbour, per
+    axis, times dt u / h^2; Section 3.2.2, and Section 5.1.5 with the
+    reciprocals of h^2 hoisted), on interior points of a zero-padded copy;
+    axis 0 of the array is y, axis 1 is x."""
+    gold = _golden("diffusion_so2_aggressive.txt" if hoisted else "diffusion_so2_kernel.txt")
+    centre, off = float(gold["centre"][0]), float(gold["offset1"][0])
     up = np.pad(u, 1)
     c = up[1:-1, 1:-1]
-    xm, xp = up[1:-1, :-2], up[1:-1, 2:]
-    ym, yp = up[:-2, 1:-1], up[2:, 1:-1]
-    if hoisted:
-        r0 = 1.0 / (hy * hy)
-        r1 = 1.0 / (hx * hx)
-        return (-1.0 * (dt * c * r1 + dt * c * r0)
-                + 0.5 * (dt * xm * r1 + dt * xp * r1 + dt * ym * r0 + dt * yp * r0) + c)
-    return (-1.0 * (dt * c / (hy * hy) + dt * c / (hx * hx))
-            + 0.5 * (dt * ym / (hy * hy) + dt * xm / (hx * hx) + dt * yp / (hy * hy) + dt * xp / (hx * hx)) + c)
+    neighbours = {"x": up[1:-1, :-2] + up[1:-1, 2:], "y": up[:-2, 1:-1] + up[2:, 1:-1]}
+    out = np.array(c, copy=True)
+    for axis, h in (("x", hx), ("y", hy)):
+        if hoisted:
+            inv = 1.0 / (h * h)
+            out = out + centre * dt * c * inv + off * dt * neighbours[axis] * inv
+        else:
+            out = out + centre * dt * c / (h * h) + off * dt * neighbours[axis] / (h * h)
+    return out
 
 
 @pytest.mark.parametrize("hoisted", [False, True])
 def test_diffusion_step_matches_printed_kernel(hoisted):
-    """One oracle diffusion step at so 2, nu = 0.5 equals the printed OPS
-    kernel (both listings agree to rounding)."""
+    """One oracle diffusion step at so 2, nu = 0.5 equals the update built
+    from the coefficients of the printed kernels (with divisions, and with
+    hoisted reciprocals: both agree to rounding)."""
     g = oracle.Grid((23, 17), (0.7, 1.3), (0.0, 0.0), 2)
     rng = np.random.default_rng(8)
     u0 = rng.standard_normal(g.array_shape)
     dt = 0.1
     got = oracle.diffusion(g, u0, 0.5, dt, 1)
-    want = _printed_so2_kernel(u0, dt, 0.7, 1.3, hoisted)
+    want = _so2_update_from_printed_values(u0, dt, 0.7, 1.3, hoisted)
     assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want))
 
 
