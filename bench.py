@@ -259,6 +259,30 @@ def bench_precision(torch, dev, stream, ref_rec):
     return res
 
 
+def bench_adjoint(torch, dev, stream):
+    """fd_adjoint on layered3d_256: the traces of a forward run injected back
+    at the 256 receivers, F^T sampled at the source (same 16 B per point and
+    step as the forward)."""
+    from paper_1906_10811_amd import Grid
+    w, v, wav = make_workload("layered3d_256", torch, dev)
+    g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], stream=stream)
+    rec = g.forward(w["src"], wav, w["rec"], w["dt"], stream=stream)
+    g.adjoint(w["src"], w["rec"], rec, w["dt"], stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        g.adjoint(w["src"], w["rec"], rec, w["dt"], stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1000.0
+    gp = g.padded_points * w["nt"] / secs / 1e9
+    g.close()
+    return dict(gpts=round(gp, 1), ms=round(secs * 1000.0, 2), b_alg_per_pt=B_STEP,
+                frac_hbm=round(gp * B_STEP / HBM_PEAK_GBS, 4))
+
+
 def bench_sinc(torch, dev, stream):
     """layered3d_256 forward with Kaiser-windowed sinc sources and receivers
     (half-width 4 and 8: 512 and 4096 nodes per point) instead of the
@@ -389,7 +413,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of gradient,precision,serving,diffusion,sinc or all/none")
+                    help="comma list of adjoint,gradient,precision,serving,diffusion,sinc or all/none")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box in this setup has a single MI355X, and the "
@@ -403,7 +427,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
     extras = set(args.extras.split(",")) if args.extras not in ("all", "none") else (
-        {"gradient", "precision", "serving", "diffusion", "sinc"} if args.extras == "all" else set())
+        {"adjoint", "gradient", "precision", "serving", "diffusion", "sinc"} if args.extras == "all" else set())
 
     copy_gbs = copy_probe(torch, dev, stream)
     log("stream copy: %.0f GB/s" % copy_gbs)
@@ -443,6 +467,9 @@ def main():
         _, ref = time_forward(torch, g, w2, wav2, 1, 0, stream)
         g.close()
         line["precision"] = bench_precision(torch, dev, stream, ref)
+    if "adjoint" in extras:
+        log("adjoint: layered3d_256")
+        line["adjoint"] = bench_adjoint(torch, dev, stream)
     if "sinc" in extras:
         log("windowed-sinc sparse points")
         line["sinc"] = bench_sinc(torch, dev, stream)
