@@ -146,8 +146,8 @@ def bench_cpu_baseline(w):
     t0 = time.perf_counter()
     oracle.forward(og, vp, sig, w["dt"], nt, w["src"], wav[:nt], w["rec"])
     t1 = time.perf_counter()
-    # scale to about 12 s of work
-    nt2 = max(2, min(1000, int(12.0 / max(1e-3, (t1 - t0) / nt))))
+    # scale to about 15 s of work (the 2-step probe overestimates a step)
+    nt2 = max(2, min(1000, int(24.0 / max(1e-3, (t1 - t0) / nt))))
     t0 = time.perf_counter()
     oracle.forward(og, vp, sig, w["dt"], nt2, w["src"], wav[:nt2], w["rec"])
     t1 = time.perf_counter()
