@@ -861,8 +861,14 @@ extern "C" int fd_adjoint(fd_grid *g, const fd_shot *sh, int nt, double dt,
     HIPCHK(launch_zero_field(L, g->uB, g->st, s));
     StepArgs a = base_args(g);
     void *A = g->uA, *B = g->uB;   // lambda^k, lambda^{k+1}
-    const float inj_scale = (float)(g->amp / (dt * dt));
-    const float smp_scale = (float)(dt * dt / (g->cell * g->amp));
+    // 16-bit storage keeps amp_adj * lambda.  lambda is of order v^2 r, not
+    // dt^2 v^2 w / prod(h) like the forward field, so the forward's scale
+    // times dt^2 / prod(h) (rounded to a power of two, exact) keeps the
+    // stored adjoint field in range; float32 storage is not scaled.
+    const double amp_adj = g->st == Store::F32 ? 1.0
+                                               : std::exp2(std::round(std::log2((double)g->amp * dt * dt / g->cell)));
+    const float inj_scale = (float)(amp_adj / (dt * dt));
+    const float smp_scale = (float)(dt * dt / (g->cell * amp_adj));
     for (int k = nt; k >= 1; --k) {
         a.u = A;
         a.prev = B;

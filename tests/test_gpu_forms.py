@@ -201,3 +201,34 @@ def test_storage_error_growth_over_1500_steps():
           {k: ["%.2e" % e for e in v] for k, v in rows.items()}, flush=True)
     assert max(rows["f32"]) <= 1e-5
     assert max(rows["f16"]) <= 5e-3 and max(rows["bf16"]) <= 5e-2
+
+
+@pytest.mark.parametrize("storage,tol", [("f16", 1e-2), ("bf16", 5e-2)])
+def test_reduced_precision_2d_and_adjoint(storage, tol):
+    """16-bit storage through the 2D step kernel (forward) and through the
+    3D adjoint (residual injected at the receivers, F^T sampled at the
+    sources), each against the FP64 oracle at the per-storage bound."""
+    need_gpu()
+    from gpu_common import case, gpu_grid, oracle_forward
+    c2 = case((90, 77), 8, 6, 150, seed=21, nsrc=2, nrec=11)
+    want2, *_ = oracle_forward(c2)
+    dev = torch.device("cuda:0")
+    g2 = gpu_grid(c2, storage=storage)
+    got2 = g2.forward(c2["src"], torch.from_numpy(c2["wav"]).to(dev), c2["rec"], c2["dt"])
+    torch.cuda.synchronize()
+    e2 = rel_l2(got2.cpu().numpy(), want2)
+    g2.close()
+    c3 = case((40, 33, 26), 8, 4, 80, seed=22, nsrc=2, nrec=9)
+    og = c3["og"]
+    vp = oracle.pad_velocity(og, c3["v"])
+    sig = oracle.damping(og, oracle.sigma_max_default(og, float(vp.max())))
+    rng = np.random.default_rng(5)
+    res = rng.standard_normal((c3["nt"], len(c3["rec"])))
+    want3, _ = oracle.adjoint(og, vp, sig, c3["dt"], c3["nt"], c3["src"], c3["rec"], res)
+    g3 = gpu_grid(c3, storage=storage)
+    got3 = g3.adjoint(c3["src"], c3["rec"], torch.from_numpy(res.astype(np.float32)).to(dev), c3["dt"])
+    torch.cuda.synchronize()
+    e3 = rel_l2(got3.cpu().numpy(), want3)
+    g3.close()
+    print("%s: 2D forward %.3e, 3D adjoint %.3e" % (storage, e2, e3), flush=True)
+    assert e2 <= tol and e3 <= tol

@@ -120,3 +120,29 @@ def test_ticket_is_collected_once():
             srv.wait(bad, timeout=5.0)
         assert e.value.code == -1
     srv.close()
+
+
+def test_mixed_storage_requests_equal_alone():
+    """F16, BF16 and FP32 requests resident together: each result equals the
+    same shot run alone with its storage type (bitwise)."""
+    need_gpu()
+    from paper_1906_10811_amd import Grid, Server
+    reqs = _requests(6, seed=17)
+    for k, r in enumerate(reqs):
+        r["storage"] = ["f32", "f16", "bf16"][k % 3]
+    dev = torch.device("cuda:0")
+    alone = []
+    for r in reqs:
+        g = Grid(r["shape"], r["spacing"], torch.from_numpy(r["vp"]).to(dev), space_order=r["space_order"],
+                 nbl=r["nbl"], storage=r["storage"])
+        out = g.forward(r["src_xyz"], torch.from_numpy(r["wavelet"]).to(dev), r["rec_xyz"], r["dt"])
+        torch.cuda.synchronize()
+        alone.append(out.cpu().numpy())
+        g.close()
+    srv = Server(1 << 31, max_slots=4, steps_per_round=16)
+    tickets = [srv.submit(**r) for r in reqs]
+    res = [srv.wait(t, timeout=120.0) for t in tickets]
+    srv.close()
+    for k, ((out, info), ref) in enumerate(zip(res, alone)):
+        assert info["status"] == 0
+        assert np.array_equal(out, ref), "request %d (%s) differs from its lone run" % (k, reqs[k]["storage"])
