@@ -227,34 +227,38 @@ class _Modeling(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, vp_padded, wavelet, shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt,
-                checkpoint_every):
-        g = Grid(shape, spacing, vp_padded, space_order=space_order, nbl=nbl, vp_padded=True)
+                checkpoint_every, sinc_radius):
+        g = Grid(shape, spacing, vp_padded, space_order=space_order, nbl=nbl, vp_padded=True,
+                 sinc_radius=sinc_radius)
         rec = g.forward(src_xyz, wavelet, rec_xyz, dt)
         ctx.save_for_backward(vp_padded, wavelet)
-        ctx.cfg = (shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, checkpoint_every)
+        ctx.cfg = (shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, checkpoint_every, sinc_radius)
         g.close()
         return rec
 
     @staticmethod
     def backward(ctx, grad_rec):
         vp_padded, wavelet = ctx.saved_tensors
-        shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, K = ctx.cfg
-        g = Grid(shape, spacing, vp_padded, space_order=space_order, nbl=nbl, vp_padded=True)
+        shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, K, sinc_radius = ctx.cfg
+        g = Grid(shape, spacing, vp_padded, space_order=space_order, nbl=nbl, vp_padded=True,
+                 sinc_radius=sinc_radius)
         _, g_m, _, g_w = g.gradient(src_xyz, wavelet, rec_xyz, grad_rec.contiguous(), dt,
                                     checkpoint_every=K, residual_given=True, want_src_adj=True)
         torch.cuda.current_stream().synchronize()
         g.close()
         v = vp_padded.to(torch.float64)
         g_v = (g_m * (-2.0 / v ** 3)).to(vp_padded.dtype)
-        return g_v, g_w.to(wavelet.dtype).reshape(wavelet.shape), None, None, None, None, None, None, None, None
+        return g_v, g_w.to(wavelet.dtype).reshape(wavelet.shape), None, None, None, None, None, None, None, None, None
 
 
 def modeling(vp_padded: torch.Tensor, wavelet: torch.Tensor, shape, spacing, space_order: int,
-             nbl: int, src_xyz, rec_xyz, dt: float, checkpoint_every: int = 50) -> torch.Tensor:
+             nbl: int, src_xyz, rec_xyz, dt: float, checkpoint_every: int = 50,
+             sinc_radius: int = 0) -> torch.Tensor:
     """Differentiable forward modelling: traces [nt, nrec] from the velocity
-    on the padded grid and the wavelets [nt, nsrc]."""
+    on the padded grid and the wavelets [nt, nsrc] (sparse points multilinear,
+    or windowed sinc of the given half-width)."""
     return _Modeling.apply(vp_padded, wavelet, tuple(shape), tuple(spacing), space_order, nbl,
-                           src_xyz, rec_xyz, dt, checkpoint_every)
+                           src_xyz, rec_xyz, dt, checkpoint_every, int(sinc_radius))
 
 
 class Server:

@@ -57,7 +57,8 @@ def test_reduced_precision_storage_error_vs_fp64():
     assert errs["f16 weak, scale 1e4*auto"] <= 5e-3
 
 
-def test_autograd_modeling_matches_oracle_gradient():
+@pytest.mark.parametrize("sinc", [0, 3])
+def test_autograd_modeling_matches_oracle_gradient(sinc):
     """loss = 1/2 |F(v, w) - d|^2 through torch.autograd: d loss/d v equals
     the oracle's O12 gradient chained through m = 1/v^2, and d loss/d w
     equals the oracle's adjoint of the residual."""
@@ -74,14 +75,14 @@ def test_autograd_modeling_matches_oracle_gradient():
     wav = synth.ricker(nt, dt, 30.0)[:, None]
     v_true = vp.copy()
     v_true[8:20, :, :] *= 1.08
-    d_obs, *_ = oracle.forward(g0, v_true, sig, dt, nt, src, wav, rec)
-    J, g_m, rec0 = oracle.gradient(g0, vp, sig, dt, nt, src, wav, rec, d_obs)
+    d_obs, *_ = oracle.forward(g0, v_true, sig, dt, nt, src, wav, rec, sinc_radius=sinc)
+    J, g_m, rec0 = oracle.gradient(g0, vp, sig, dt, nt, src, wav, rec, d_obs, sinc_radius=sinc)
     r = rec0 - d_obs
-    g_w, _ = oracle.adjoint(g0, vp, sig, dt, nt, src, rec, r)
+    g_w, _ = oracle.adjoint(g0, vp, sig, dt, nt, src, rec, r, sinc_radius=sinc)
     dev = torch.device("cuda:0")
     vt = torch.tensor(vp, dtype=torch.float32, device=dev, requires_grad=True)
     wt = torch.tensor(wav, dtype=torch.float32, device=dev, requires_grad=True)
-    out = modeling(vt, wt, shape, h, so, nbl, src, rec, dt, checkpoint_every=30)
+    out = modeling(vt, wt, shape, h, so, nbl, src, rec, dt, checkpoint_every=30, sinc_radius=sinc)
     loss = 0.5 * ((out.double() - torch.tensor(d_obs, device=dev)) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
@@ -89,7 +90,7 @@ def test_autograd_modeling_matches_oracle_gradient():
     ev = rel_l2(vt.grad.cpu().numpy(), g_v_want)
     ew = rel_l2(wt.grad.cpu().numpy(), g_w)
     eJ = abs(float(loss.item()) - J) / J
-    print("autograd: loss %.3e, dv %.3e, dw %.3e" % (eJ, ev, ew))
+    print("autograd sinc=%d: loss %.3e, dv %.3e, dw %.3e" % (sinc, eJ, ev, ew))
     # the wavelet gradient is F^T of a float32 residual that is ~10x smaller
     # than the traces it is the difference of: gradient-class gate 1e-4
     assert eJ <= 1e-4 and ev <= 1e-4 and ew <= 1e-4
