@@ -57,8 +57,12 @@ template <Store S> struct Elem;
 
 template <> struct Elem<Store::F32> {
     using T = float;
+    using Raw = float4;   // 4 points as loaded (converted to float4 only where used)
     __device__ static float4 ld4(const T *p) { return *reinterpret_cast<const float4 *>(p); }
     __device__ static float4 ld4nt(const T *p) { return ld4nt_f32(p); }
+    __device__ static Raw ld4raw(const T *p) { return ld4(p); }
+    __device__ static Raw ld4ntraw(const T *p) { return ld4nt(p); }
+    __device__ static float4 cvt(const Raw &r) { return r; }
     __device__ static void st4nt(T *p, float4 v) { st4nt_f32(p, v); }
     __device__ static float ld(const T *p) { return *p; }
     __device__ static void st(T *p, float v) { *p = v; }
@@ -84,8 +88,15 @@ template <typename Cvt> struct Elem16 {
         return make_uint2((uint32_t)Cvt::from_f(v.x) | ((uint32_t)Cvt::from_f(v.y) << 16),
                           (uint32_t)Cvt::from_f(v.z) | ((uint32_t)Cvt::from_f(v.w) << 16));
     }
+    using Raw = uint2;
     __device__ static float4 ld4(const T *p) { return unpack(*reinterpret_cast<const uint2 *>(p)); }
     __device__ static float4 ld4nt(const T *p) { return unpack(ld2nt_u32(p)); }
+    // Raw loads keep the 16-bit pairs in registers; the unpack happens where
+    // the values are used, so a prefetch issued planes ahead does not wait
+    // for its data at the load.
+    __device__ static Raw ld4raw(const T *p) { return *reinterpret_cast<const uint2 *>(p); }
+    __device__ static Raw ld4ntraw(const T *p) { return ld2nt_u32(p); }
+    __device__ static float4 cvt(const Raw &r) { return unpack(r); }
     __device__ static void st4nt(T *p, float4 v) { st2nt_u32(p, pack(v)); }
     __device__ static float ld(const T *p) { return Cvt::to_f(*p); }
     __device__ static void st(T *p, float v) { *p = Cvt::from_f(v); }
@@ -358,20 +369,22 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     // plane z+2 are in flight while plane z is computed (two planes ahead);
     // the loop is unrolled by three so the rotation needs no register moves,
     // which would otherwise wait for the loads they move.
+    using Raw = typename E::Raw;
     struct PlaneRegs {
-        float4 front, pv, mv;
-        float4 hv[HPT];   // halo of plane z+R
+        Raw front, mv;
+        float4 pv;
+        Raw hv[HPT];      // halo of plane z+R
         float4 br, gp;    // imaging step: bracket and partial gradient of plane z
     };
     auto issue = [&](PlaneRegs &r, int st) {
         st = min(st, len - 1);   // past the chunk: a harmless in-bounds reload
         const long long zo = (long long)(zs + dir * st) * plane;
         const long long fo = zo + (long long)(dir * R) * plane;   // the queue front, R planes ahead
-        r.front = E::ld4(U + base + fo);
+        r.front = E::ld4raw(U + base + fo);
 #pragma unroll
-        for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4(U + hoff[k] + fo);
+        for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4raw(U + hoff[k] + fo);
         r.pv = ld4nt_f32(Pp + base + zo);
-        r.mv = E::ld4nt(Pv + base + zo);
+        r.mv = E::ld4ntraw(Pv + base + zo);
         if constexpr (MODE == kImage) {
             r.br = ld4nt_f32(a.img.br_in + base + zo);
             r.gp = ld4nt_f32(a.img.gpart + base + zo);
@@ -380,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     auto body = [&](int st, const PlaneRegs &cur, PlaneRegs &ahead) {
         const int z = zs + dir * st;
         float4 *buf = lds[st & 1];
-        q[2 * R] = cur.front;
+        q[2 * R] = E::cvt(cur.front);
         buf[(R + ty) * W4 + HX4 + tx] = q[R];
         // park the halo of plane z+R (fetched with the front of the same
         // plane) and stage the halo of plane z parked R planes ago
@@ -389,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
 #pragma unroll
         for (int k = 0; k < HPT; ++k) {
             if (hl[k] >= 0) {
-                ring_w[k * kBlock] = cur.hv[k];
+                ring_w[k * kBlock] = E::cvt(cur.hv[k]);
                 buf[hl[k]] = ring_r[k * kBlock];
             }
         }
@@ -407,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         }
 
         if (active) {
+            const float4 mvf = E::cvt(cur.mv);
             // x neighbours: 2*HX4+1 float4 chunks of the lane's LDS row
             float xs[4 * (2 * HX4 + 1)];
             const float4 *row = buf + (R + ty) * W4 + HX4 + tx;
@@ -437,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             float un[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                un[i] = update_point(comp(q[R], i), comp(cur.mv, i), comp(cur.pv, i), lap[i], src[i],
+                un[i] = update_point(comp(q[R], i), comp(mvf, i), comp(cur.pv, i), lap[i], src[i],
                                      sxy[i] + sz);
             const long long off = base + (long long)z * plane;
             const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
@@ -458,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
                 float sv[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) sv[i] = sxy[i] + sz;
-                grad_epilogue<MODE>(a.img, off, nvalid, un, q[R], cur.mv, sv);
+                grad_epilogue<MODE>(a.img, off, nvalid, un, q[R], mvf, sv);
             } else if constexpr (MODE == kImage) {
                 image_accumulate(a.img.gpart + off, nvalid, un, cur.br, cur.gp);
             }
