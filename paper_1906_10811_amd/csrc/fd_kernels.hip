@@ -68,15 +68,15 @@ template <> struct Elem<Store::F32> {
     __device__ static void st(T *p, float v) { *p = v; }
 };
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 __device__ inline float h2f(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
 __device__ inline uint16_t f2h(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
-// bfloat16: upper half of the float32 pattern, round to nearest even.
+// bfloat16: the upper half of the float32 pattern; float32 -> bfloat16
+// rounds to nearest even in hardware (v_cvt_pk_bf16_f32 converts a pair).
 __device__ inline float b2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-__device__ inline uint16_t f2b(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+__device__ inline uint16_t f2b(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 template <typename Cvt> struct Elem16 {
     using T = uint16_t;
@@ -84,10 +84,7 @@ template <typename Cvt> struct Elem16 {
         return make_float4(Cvt::to_f(v.x & 0xFFFF), Cvt::to_f(v.x >> 16), Cvt::to_f(v.y & 0xFFFF),
                            Cvt::to_f(v.y >> 16));
     }
-    __device__ static uint2 pack(float4 v) {
-        return make_uint2((uint32_t)Cvt::from_f(v.x) | ((uint32_t)Cvt::from_f(v.y) << 16),
-                          (uint32_t)Cvt::from_f(v.z) | ((uint32_t)Cvt::from_f(v.w) << 16));
-    }
+    __device__ static uint2 pack(float4 v) { return make_uint2(Cvt::pack2(v.x, v.y), Cvt::pack2(v.z, v.w)); }
     using Raw = uint2;
     __device__ static float4 ld4(const T *p) { return unpack(*reinterpret_cast<const uint2 *>(p)); }
     __device__ static float4 ld4nt(const T *p) { return unpack(ld2nt_u32(p)); }
@@ -104,10 +101,15 @@ template <typename Cvt> struct Elem16 {
 struct CvtF16 {
     __device__ static float to_f(uint32_t h) { return h2f((uint16_t)h); }
     __device__ static uint16_t from_f(float f) { return f2h(f); }
+    __device__ static uint32_t pack2(float a, float b) { return (uint32_t)f2h(a) | ((uint32_t)f2h(b) << 16); }
 };
 struct CvtBF16 {
     __device__ static float to_f(uint32_t b) { return b2f((uint16_t)b); }
     __device__ static uint16_t from_f(float f) { return f2b(f); }
+    __device__ static uint32_t pack2(float a, float b) {
+        const f32x2 v = {a, b};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+    }
 };
 template <> struct Elem<Store::F16> : Elem16<CvtF16> {};
 template <> struct Elem<Store::BF16> : Elem16<CvtBF16> {};
