@@ -283,6 +283,30 @@ def bench_adjoint(torch, dev, stream):
                 frac_hbm=round(gp * B_STEP / HBM_PEAK_GBS, 4))
 
 
+def bench_grf512(torch, dev, stream):
+    """The precision workload at full size: grf3d_512 (512^3 + 40 damping =
+    592^3 padded, Gaussian random field, so 8, 1500 steps), one forward each
+    with FP32, F16 (automatic scale) and BF16 wavefields; 16-bit traces are
+    compared with the FP32 run (their error against the FP64 oracle is
+    measured at a size the oracle can run, in the tests)."""
+    from paper_1906_10811_amd import Grid
+    w, v, wav = make_workload("grf3d_512", torch, dev)
+    res, ref = {}, None
+    for st in ("f32", "f16", "bf16"):
+        g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, stream=stream)
+        secs, rec = time_forward(torch, g, w, wav, 1, 0, stream)
+        gp = g.padded_points * w["nt"] / secs / 1e9
+        b = B_STEP if st == "f32" else 10.0
+        res[st] = dict(gpts=round(gp, 1), frac_hbm=round(gp * b / HBM_PEAK_GBS, 4), b_alg_per_pt=b)
+        if st == "f32":
+            ref = rec.double()
+        else:
+            res[st]["rel_l2_vs_f32"] = float((rec.double() - ref).norm() / ref.norm())
+        g.close()
+    del v
+    return res
+
+
 def bench_sinc(torch, dev, stream):
     """layered3d_256 forward with Kaiser-windowed sinc sources and receivers
     (half-width 4 and 8: 512 and 4096 nodes per point) instead of the
@@ -413,7 +437,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma list of adjoint,gradient,precision,serving,diffusion,sinc or all/none")
+                    help="comma list of adjoint,gradient,precision,grf512,serving,diffusion,sinc or all/none")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box in this setup has a single MI355X, and the "
@@ -427,7 +451,8 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
     extras = set(args.extras.split(",")) if args.extras not in ("all", "none") else (
-        {"adjoint", "gradient", "precision", "serving", "diffusion", "sinc"} if args.extras == "all" else set())
+        {"adjoint", "gradient", "precision", "grf512", "serving", "diffusion", "sinc"} if args.extras == "all"
+        else set())
 
     copy_gbs = copy_probe(torch, dev, stream)
     log("stream copy: %.0f GB/s" % copy_gbs)
@@ -467,6 +492,9 @@ def main():
         _, ref = time_forward(torch, g, w2, wav2, 1, 0, stream)
         g.close()
         line["precision"] = bench_precision(torch, dev, stream, ref)
+    if "grf512" in extras:
+        log("precision workload at full size: grf3d_512")
+        line["grf512"] = bench_grf512(torch, dev, stream)
     if "adjoint" in extras:
         log("adjoint: layered3d_256")
         line["adjoint"] = bench_adjoint(torch, dev, stream)
