@@ -92,7 +92,8 @@ typedef struct fd_grid_desc {
                               replication; 1: vp given on the padded grid */
     int max_src;           /* capacity of the source table (points), 0 selects 64 */
     int max_rec;           /* capacity of the receiver table (points), 0 selects 4096 */
-    int zchunk;            /* planes marched per workgroup in 3D, 0 selects automatically */
+    int zchunk;            /* planes marched per workgroup in 3D (at most 512, larger values are
+                              clamped), 0 selects automatically */
     int sinc_radius;       /* 0: multilinear sparse weights; 1..8: Kaiser-windowed sinc
                               over (2 sinc_radius)^ndim nodes per point (the sparse
                               tables, about 36 B per node, scale with max_src and

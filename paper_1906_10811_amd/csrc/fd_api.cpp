@@ -678,11 +678,11 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
                     nzc = n;
                 }
             }
+            // Wide xy planes give long chunks (592^3: 370 tiles, k = 3, two
+            // chunks of 296 planes); measured against chunks of 64 planes
+            // there, one round of long chunks is as fast in float32 and 3 %
+            // faster in bfloat16.
             zc = (L.nz + nzc - 1) / nzc;
-            // Wide xy planes leave few chunks per round; long chunks then
-            // lose more to the round tail than short ones lose to their
-            // 2r warm-up planes (measured: 592^3, so 8).
-            if (zc > 128) zc = 64;
         }
         g->zchunk[m] = std::min(std::min(zc, L.nz), kMaxChunk);
         g->ntz[m] = (L.nz + g->zchunk[m] - 1) / g->zchunk[m];

@@ -15,7 +15,7 @@ constexpr int kTileX = 64;        // x points per tile (16 lanes x 4 points)
 constexpr int kTileY = 16;        // y rows per 3D tile (one row per 16 lanes)
 constexpr int kTile2Z = 64;       // z rows per 2D tile
 constexpr int kBlock = 256;       // threads per workgroup
-constexpr int kMaxChunk = 256;    // z planes per 3D workgroup at most
+constexpr int kMaxChunk = 512;    // z planes per 3D workgroup at most
 
 // Pitched device layout of one field: rows of `pitch` elements, x = 0 at
 // element kXOff; `yh` zero rows above and below each plane (r in 3D, 0 in

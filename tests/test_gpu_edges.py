@@ -102,10 +102,11 @@ def test_receiver_table_capacity():
     assert torch.equal(rec, rec2)
 
 
-@pytest.mark.parametrize("shape,zchunk", [((30, 20, 24), 1), ((20, 18, 300), 256)])
+@pytest.mark.parametrize("shape,zchunk", [((30, 20, 24), 1), ((20, 18, 560), 512), ((20, 18, 560), 2000)])
 def test_extreme_z_chunks(shape, zchunk):
-    """One plane per workgroup (every plane a chunk start, warm-up only), and
-    the longest chunk the kernel stages (256 planes, then a ragged 52)."""
+    """One plane per workgroup (every plane a chunk start, warm-up only), the
+    longest chunk the kernel stages (512 planes, then a ragged 52), and a
+    request beyond it, which is clamped to 512."""
     need_gpu()
     c = case(shape, 8, 2, 30, seed=9, nsrc=2, nrec=7)
     want, u_nt, _, _ = oracle_forward(c)
