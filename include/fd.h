@@ -99,6 +99,8 @@ typedef struct fd_grid_desc {
                               tables, about 36 B per node, scale with max_src and
                               max_rec: 3D radius 8 with 4096 receivers is 0.6 GB) */
     double sinc_beta;      /* Kaiser shape b; <= 0 selects pi * sinc_radius / 2 */
+    int tile_x;            /* 3D workgroup tile in x points: 64 (64 x 16 xy tiles) or 32
+                              (32 x 32); 0 selects automatically; ignored in 2D */
 } fd_grid_desc;
 
 /* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
@@ -127,6 +129,9 @@ typedef struct fd_grid_info {
     double critical_dt;    /* von Neumann limit of the undamped update */
     double damp_max;       /* sigma_max in use, 1/s */
     size_t field_bytes;    /* one wavefield buffer as laid out on the device */
+    int tile[2];           /* 3D: xy tile of the step workgroups in points (64 x 16 or
+                              32 x 32); 2D: (64, 64), x points and z rows */
+    int zchunk;            /* 3D: z planes per workgroup of a plain step; 2D: 64 */
 } fd_grid_info;
 
 typedef struct fd_grid fd_grid;

@@ -54,7 +54,7 @@ class Grid:
     def __init__(self, shape, spacing, vp: torch.Tensor, space_order: int = 8, nbl: int = 0,
                  origin=None, damp_max: float = 0.0, storage: str = "f32", amp_scale: float = 0.0,
                  vp_padded: bool = False, max_src: int = 0, max_rec: int = 0, zchunk: int = 0,
-                 sinc_radius: int = 0, sinc_beta: float = 0.0, stream=None):
+                 sinc_radius: int = 0, sinc_beta: float = 0.0, tile_x: int = 0, stream=None):
         lib = _lib.load()
         ndim = len(shape)
         self.ndim = ndim
@@ -75,6 +75,7 @@ class Grid:
         d.zchunk = int(zchunk)
         d.sinc_radius = int(sinc_radius)
         d.sinc_beta = float(sinc_beta)
+        d.tile_x = int(tile_x)
         self.desc = d
         nbytes = ctypes.c_size_t()
         _lib.check(lib.fd_grid_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
@@ -97,6 +98,8 @@ class Grid:
         self.critical_dt = info.critical_dt
         self.damp_max = info.damp_max
         self.field_bytes = int(info.field_bytes)
+        self.tile = (int(info.tile[0]), int(info.tile[1]))
+        self.zchunk = int(info.zchunk)
 
     @property
     def array_shape(self):

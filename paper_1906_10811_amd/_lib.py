@@ -54,6 +54,7 @@ class GridDesc(ctypes.Structure):
         ("zchunk", ctypes.c_int),
         ("sinc_radius", ctypes.c_int),
         ("sinc_beta", ctypes.c_double),
+        ("tile_x", ctypes.c_int),
     ]
 
 
@@ -85,6 +86,8 @@ class GridInfo(ctypes.Structure):
         ("critical_dt", ctypes.c_double),
         ("damp_max", ctypes.c_double),
         ("field_bytes", ctypes.c_size_t),
+        ("tile", ctypes.c_int * 2),
+        ("zchunk", ctypes.c_int),
     ]
 
 

@@ -109,6 +109,8 @@ bool fdi_check_desc(const fd_grid_desc *d) {
     if (d->storage < 0 || d->storage > 2) return fdi_fail(FD_ERR_ARG, "storage"), false;
     if (d->amp_scale < 0.f || !std::isfinite(d->amp_scale)) return fdi_fail(FD_ERR_ARG, "amp_scale"), false;
     if (d->max_src < 0 || d->max_rec < 0 || d->zchunk < 0) return fdi_fail(FD_ERR_ARG, "capacities"), false;
+    if (d->tile_x != 0 && d->tile_x != 32 && d->tile_x != 64)
+        return fdi_fail(FD_ERR_ARG, "tile_x must be 0, 32 or 64"), false;
     if (d->sinc_radius < 0 || d->sinc_radius > kMaxSincR)
         return fdi_fail(FD_ERR_ARG, "sinc_radius must be 0..%d", kMaxSincR), false;
     if (!std::isfinite(d->sinc_beta)) return fdi_fail(FD_ERR_ARG, "sinc_beta"), false;
@@ -185,11 +187,32 @@ int sparse_nodes(const fd_grid_desc *d) {
     return n;
 }
 
+// Width of the 3D step tiles in float4 columns: 16 (64 x 16 points) or 8
+// (32 x 32).  The 32 x 32 shape stages 2r halo rows per 32 rows instead of
+// per 16, but each row of its x halo is one more cache-line request.
+// Measured (336^3 and 280^3, every even order): 64 x 16 is faster up to so 8
+// (by 3-11 %), 32 x 32 from so 14 on (by 4-16 %, 25 % in 16-bit at 280^3);
+// at so 10 and 12 the 32 x 32 shape wins only where 64-point rows leave many
+// lanes idle (280 = 4.375 x 64: +2 %, 16-bit +4-6 %; 336 = 5.25 x 64: -3 %).
+constexpr double kTileNarrowGain = 0.06;   // lane-use margin that selects 32 x 32 at so 10, 12
+
+int tile_w4(const fd_grid_desc *d, const Layout &L) {
+    if (L.ndim != 3 || d->tile_x == 64) return 16;
+    if (d->tile_x == 32) return 8;
+    if (L.r >= 7) return 8;
+    if (L.r <= 4) return 16;
+    auto used = [&](int tw4) {   // fraction of tile lanes that hold a grid point
+        const double tx = tile3_x(tw4), ty = tile3_y(tw4);
+        return (double)L.nx * L.ny / (std::ceil(L.nx / tx) * tx * std::ceil(L.ny / ty) * ty);
+    };
+    return used(8) > used(16) + kTileNarrowGain ? 8 : 16;
+}
+
 // Tiles of the step kernels' xy (3D) or x (2D) decomposition; the injection
 // tables keep one plane-pointer row per tile.
-int xy_tiles(const Layout &L) {
-    const int ntx = (L.nx + kTileX - 1) / kTileX;
-    const int nty = L.ndim == 3 ? (L.ny + kTileY - 1) / kTileY : 1;
+int xy_tiles(const Layout &L, int tw4) {
+    const int ntx = L.ndim == 3 ? (L.nx + tile3_x(tw4) - 1) / tile3_x(tw4) : (L.nx + kTileX - 1) / kTileX;
+    const int nty = L.ndim == 3 ? (L.ny + tile3_y(tw4) - 1) / tile3_y(tw4) : 1;
     return ntx * nty;
 }
 
@@ -197,7 +220,7 @@ WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     WsPlan w{};
     const size_t esz = d->storage == FD_STORE_F32 ? 4 : 2;
     const int nc = sparse_nodes(d);
-    const size_t nptr = (size_t)xy_tiles(L) * (L.nz + 1);
+    const size_t nptr = (size_t)xy_tiles(L, tile_w4(d, L)) * (L.nz + 1);
     w.cap_src = d->max_src ? d->max_src : 64;
     w.cap_rec = d->max_rec ? d->max_rec : 4096;
     w.field_bytes = align_up((size_t)L.elems * esz, 256);
@@ -253,6 +276,7 @@ struct fd_grid {
     hipEvent_t stage_ev;
     bool stage_pending;
     int ntx, nty;
+    int tw4;                 // 3D tile width in float4 columns (16 or 8)
     int ntz[3], zchunk[3];   // per step mode (kPlain, kBracket, kImage)
     hipStream_t last_stream;   // stream of the latest enqueued work
     bool has_last_stream;
@@ -426,7 +450,7 @@ int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s
             if (ndim == 3) { y = ix[1]; z = ix[2]; } else { z = ix[1]; }
             idx[slot] = L.offset(x, y, z);
             w[slot] = (float)wt;
-            const int tile = (ndim == 3 ? (y / kTileY) * g->ntx : 0) + x / kTileX;
+            const int tile = ndim == 3 ? (y / tile3_y(g->tw4)) * g->ntx + x / tile3_x(g->tw4) : x / kTileX;
             if ((float)wt != 0.f) ents.push_back({tile, z, y, x, p, (float)wt});
         }
     }
@@ -512,6 +536,7 @@ StepArgs base_args(const fd_grid *g) {
     }
     a.ntx = g->ntx;
     a.nty = g->nty;
+    a.tile_w4 = g->tw4;
     a.ntz = g->ntz[kPlain];
     a.zchunk = g->zchunk[kPlain];
     return a;
@@ -640,8 +665,9 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
 
     // launch geometry of each step mode (the gradient modes differ in
     // register use, hence occupancy, hence chunking)
-    g->ntx = (L.nx + kTileX - 1) / kTileX;
-    g->nty = desc->ndim == 3 ? (L.ny + kTileY - 1) / kTileY : 1;
+    g->tw4 = tile_w4(desc, L);
+    g->ntx = desc->ndim == 3 ? (L.nx + tile3_x(g->tw4) - 1) / tile3_x(g->tw4) : (L.nx + kTileX - 1) / kTileX;
+    g->nty = desc->ndim == 3 ? (L.ny + tile3_y(g->tw4) - 1) / tile3_y(g->tw4) : 1;
     for (int m = 0; m < 3; ++m) {
         if (desc->ndim == 2) {
             g->zchunk[m] = kTile2Z;
@@ -664,7 +690,7 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
                 cus <= 0)
                 cus = 256;
-            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m));
+            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m, g->tw4));
             const int tiles = std::max(1, g->ntx * g->nty);
             const int kmax = std::min(occ, 3), prefer = g->st == Store::F32 ? 2 : 3;
             int nzc = 1;
@@ -758,6 +784,9 @@ extern "C" int fd_grid_get_info(const fd_grid *g, fd_grid_info *info) {
     info->critical_dt = g->dt_crit;
     info->damp_max = g->sigma_max;
     info->field_bytes = g->wp.field_bytes;
+    info->tile[0] = g->d.ndim == 3 ? tile3_x(g->tw4) : kTileX;
+    info->tile[1] = g->d.ndim == 3 ? tile3_y(g->tw4) : kTile2Z;
+    info->zchunk = g->zchunk[kPlain];
     return FD_OK;
 }
 

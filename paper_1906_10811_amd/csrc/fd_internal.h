@@ -11,11 +11,15 @@ namespace fd {
 constexpr int kMaxR = 8;          // space order 16
 constexpr int kMaxSincR = 8;      // windowed-sinc half-width of sparse points
 constexpr int kXOff = 64;         // elements before x = 0 in every row (>= kMaxR, 128-B aligned)
-constexpr int kTileX = 64;        // x points per tile (16 lanes x 4 points)
-constexpr int kTileY = 16;        // y rows per 3D tile (one row per 16 lanes)
+constexpr int kTileX = 64;        // x points per 2D tile (16 lanes x 4 points)
 constexpr int kTile2Z = 64;       // z rows per 2D tile
 constexpr int kBlock = 256;       // threads per workgroup
 constexpr int kMaxChunk = 512;    // z planes per 3D workgroup at most
+
+// 3D step tiles have tw4 float4 columns per row: 16 (64 x 16 points) or 8
+// (32 x 32 points); either way one point quad per lane of a workgroup.
+inline int tile3_x(int tw4) { return 4 * tw4; }
+inline int tile3_y(int tw4) { return kBlock / tw4; }
 
 // Pitched device layout of one field: rows of `pitch` elements, x = 0 at
 // element kXOff; `yh` zero rows above and below each plane (r in 3D, 0 in
@@ -38,8 +42,8 @@ struct Layout {
 };
 
 // Per-tile, per-plane CSR of the grid points that receive a point-source
-// term in a step.  The tiles are those of the step kernels (64 x 16 in xy for
-// 3D, 64 in x for 2D), numbered tile = ty * ntx + tx.  Corner k lies at
+// term in a step.  The tiles are those of the step kernels (64 x 16 or
+// 32 x 32 in xy for 3D, 64 in x for 2D), numbered tile = ty * ntx + tx.  Corner k lies at
 // (x, y) of plane z inside tile t with
 //   plane_ptr[t * (nz + 1) + z] <= k < plane_ptr[t * (nz + 1) + z + 1];
 // each grid point appears at most once, and its value is
@@ -99,6 +103,7 @@ struct StepArgs {
     float wy[kMaxR + 1];
     float wz[kMaxR + 1];
     int ntx, nty, ntz;      // tiles per axis (ntz counts z chunks in 3D)
+    int tile_w4;            // 3D tile width in float4 columns (16 or 8)
     int zchunk;             // planes per 3D workgroup
     int nsamp_blocks;       // trailing workgroups that sample instead of stepping
     Inject inj;
@@ -109,7 +114,7 @@ struct StepArgs {
 enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
 
 // Resident workgroups per CU of a step kernel (0 if unknown).
-int step_blocks_per_cu(int ndim, int r, Store st, int mode);
+int step_blocks_per_cu(int ndim, int r, Store st, int mode, int tw4);
 
 // Launchers (fd_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s);

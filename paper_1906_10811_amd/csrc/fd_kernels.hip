@@ -14,8 +14,8 @@
 // the same launch.  All weights are precomputed on the host (no division in
 // the inner loop: the lesson of the aggressive-DSE kernel of Section 5.1.5).
 //
-// 3D: 2.5D blocking.  A workgroup owns a 64 x 16 xy tile and marches a chunk
-// of z planes.  Each lane keeps 4 consecutive x points and a register queue
+// 3D: 2.5D blocking.  A workgroup owns a 64 x 16 or a 32 x 32 xy tile and
+// marches a chunk of z planes.  Each lane keeps 4 consecutive x points and a register queue
 // of the 2r+1 z values of its column; the current xy plane (tile + r halo) is
 // staged through LDS (double-buffered, one barrier per plane) for the x and y
 // neighbours.  Loads of plane z+1 are issued before plane z is computed.
@@ -146,16 +146,17 @@ __device__ void sample_block(const Sample &s, const void *field, int blk) {
     if (i < s.npts && sub == 0) s.out[i] = v * s.scale;
 }
 
-// Source terms of one plane of a 3D tile: the tile's corners [e0, e1) of
-// the plane are spread over the workgroup; each lane sums the weighted
-// values of its corners into the tile-shaped LDS buffer (a grid point occurs
-// once per plane, so no two lanes write one cell).
+// Source terms of one plane of a 3D tile (TX points per row): the tile's
+// corners [e0, e1) of the plane are spread over the workgroup; each lane sums
+// the weighted values of its corners into the tile-shaped LDS buffer (a grid
+// point occurs once per plane, so no two lanes write one cell).
+template <int TX>
 __device__ inline void scatter_sources(const Inject &inj, int e0, int e1, int x0, int y0, float *s_src) {
     for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
         const int4 c = inj.corner[e];
         float v = 0.f;
         for (int k = c.z; k < c.w; ++k) v = __builtin_fmaf(inj.w[k], inj.vals[inj.src[k]], v);
-        s_src[(c.y - y0) * kTileX + (c.x - x0)] = v * inj.scale;
+        s_src[(c.y - y0) * TX + (c.x - x0)] = v * inj.scale;
     }
 }
 
@@ -245,13 +246,16 @@ __device__ inline void grad_epilogue(const Imaging &img, long long off, int nval
 }
 
 // ------------------------------------------------------------------ 3D step
-template <int R, Store S, int MODE>
+// TW float4 columns per tile row: 16 (64 x 16 tiles) or 8 (32 x 32 tiles).
+template <int R, Store S, int MODE, int TW>
 __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     using E = Elem<S>;
     using T = typename E::T;
+    constexpr int TX = 4 * TW;                // x points per tile
+    constexpr int TY = kBlock / TW;           // y rows per tile
     constexpr int HX4 = (R + 3) / 4;          // float4 halo columns per side
-    constexpr int W4 = 16 + 2 * HX4;          // float4 per LDS row
-    constexpr int LH = kTileY + 2 * R;        // LDS rows
+    constexpr int W4 = TW + 2 * HX4;          // float4 per LDS row
+    constexpr int LH = TY + 2 * R;            // LDS rows
     __shared__ float4 lds[2][LH * W4];
 
     const Layout L = a.L;
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     t /= a.ntx;
     const int by = t % a.nty;
     const int bz = t / a.nty;
-    const int x0 = bx * kTileX, y0 = by * kTileY;
+    const int x0 = bx * TX, y0 = by * TY;
     const int z0 = bz * a.zchunk;
     const int z1 = min(z0 + a.zchunk, L.nz);
     // Odd chunks march downwards: two adjacent chunks then read the warm-up
@@ -292,9 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     }
     // Source terms of the current plane, scattered by the workgroup (one
     // float4 per lane; a lane clears its cells after reading them).
-    __shared__ float4 s_src4[kTileY * kTileX / 4];
+    __shared__ float4 s_src4[TY * TX / 4];
     s_src4[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int tx = lane & 15, ty = lane >> 4;
+    const int tx = lane % TW, ty = lane / TW;
     const int x = x0 + 4 * tx, y = y0 + ty;
     const bool active = (y < L.ny) && (x < L.nx);
     // Masked lanes and halo items read a column that is zero in every row of
@@ -309,10 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     T *O = (T *)a.out;
     const float *__restrict__ Pp = a.p;
 
-    // Halo items of the staged plane: 2r rows above/below the tile (16 float4
+    // Halo items of the staged plane: 2r rows above/below the tile (TW float4
     // each) and HX4 float4 columns left/right of each tile row.
-    constexpr int NYH = 2 * R * 16;
-    constexpr int NXH = 2 * kTileY * HX4;
+    constexpr int NYH = 2 * R * TW;
+    constexpr int NXH = 2 * TY * HX4;
     constexpr int NH = NYH + NXH;
     constexpr int HPT = (NH + kBlock - 1) / kBlock;
     long long hoff[HPT];
@@ -325,20 +329,20 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         hok[k] = false;
         hoff[k] = zcol;
         if (i < NYH) {
-            const int hr = i >> 4, hc = i & 15;
-            const int ly = hr < R ? hr : kTileY + hr;
+            const int hr = i / TW, hc = i % TW;
+            const int ly = hr < R ? hr : TY + hr;
             const int gy = y0 + ly - R, gx = x0 + 4 * hc;
             hl[k] = ly * W4 + HX4 + hc;
             hok[k] = (gy >= 0) && (gy < L.ny) && (gx < L.nx);
             hoff[k] = hok[k] ? L.offset(gx, gy, 0) : zcol;
         } else if (i < NH) {
             const int j = i - NYH;
-            const int side = j / (kTileY * HX4);
-            const int rem = j - side * (kTileY * HX4);
+            const int side = j / (TY * HX4);
+            const int rem = j - side * (TY * HX4);
             const int row = rem / HX4, c = rem - row * HX4;
             const int gy = y0 + row;
-            const int gx = side == 0 ? x0 - 4 * HX4 + 4 * c : x0 + kTileX + 4 * c;
-            hl[k] = (R + row) * W4 + (side == 0 ? c : HX4 + 16 + c);
+            const int gx = side == 0 ? x0 - 4 * HX4 + 4 * c : x0 + TX + 4 * c;
+            hl[k] = (R + row) * W4 + (side == 0 ? c : HX4 + TW + c);
             hok[k] = (gy < L.ny) && (gx >= 0) && (gx < L.nx);
             hoff[k] = hok[k] ? L.offset(gx, gy, 0) : zcol;
         }
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         // tables in LDS are block-uniform: the branches below are uniform
         const int e0 = __builtin_amdgcn_readfirstlane(s_pp[z - z0]);
         const int e1 = __builtin_amdgcn_readfirstlane(s_pp[z - z0 + 1]);
-        if (e0 < e1) scatter_sources(a.inj, e0, e1, x0, y0, reinterpret_cast<float *>(s_src4));
+        if (e0 < e1) scatter_sources<TX>(a.inj, e0, e1, x0, y0, reinterpret_cast<float *>(s_src4));
         __syncthreads();
         float4 src4 = make_float4(0.f, 0.f, 0.f, 0.f);
         if (e0 < e1) {
@@ -952,9 +956,10 @@ using StepFn = void (*)(const StepArgs);
 
 template <Store S, int MODE, int... Rs>
 struct Table {
-    static StepFn get3(int r) {
+    static StepFn get3(int r, int tw4) {
         StepFn f = nullptr;
-        ((r == Rs ? (f = k_step3d<Rs, S, MODE>, 0) : 0), ...);
+        if (tw4 == 16) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 16>, 0) : 0), ...);
+        if (tw4 == 8) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 8>, 0) : 0), ...);
         return f;
     }
     static StepFn get2(int r) {
@@ -965,19 +970,19 @@ struct Table {
 };
 
 template <Store S, int MODE>
-StepFn pick(int ndim, int r) {
+StepFn pick(int ndim, int r, int tw4) {
     using Tb = Table<S, MODE, 1, 2, 3, 4, 5, 6, 7, 8>;
-    return ndim == 3 ? Tb::get3(r) : Tb::get2(r);
+    return ndim == 3 ? Tb::get3(r, tw4) : Tb::get2(r);
 }
 
 // The gradient modes exist for float32 storage only.
-StepFn pick_step(int ndim, int r, Store st, int mode) {
-    if (mode == kBracket) return st == Store::F32 ? pick<Store::F32, kBracket>(ndim, r) : nullptr;
-    if (mode == kImage) return st == Store::F32 ? pick<Store::F32, kImage>(ndim, r) : nullptr;
+StepFn pick_step(int ndim, int r, Store st, int mode, int tw4) {
+    if (mode == kBracket) return st == Store::F32 ? pick<Store::F32, kBracket>(ndim, r, tw4) : nullptr;
+    if (mode == kImage) return st == Store::F32 ? pick<Store::F32, kImage>(ndim, r, tw4) : nullptr;
     switch (st) {
-        case Store::F32: return pick<Store::F32, kPlain>(ndim, r);
-        case Store::F16: return pick<Store::F16, kPlain>(ndim, r);
-        case Store::BF16: return pick<Store::BF16, kPlain>(ndim, r);
+        case Store::F32: return pick<Store::F32, kPlain>(ndim, r, tw4);
+        case Store::F16: return pick<Store::F16, kPlain>(ndim, r, tw4);
+        case Store::BF16: return pick<Store::BF16, kPlain>(ndim, r, tw4);
     }
     return nullptr;
 }
@@ -992,7 +997,7 @@ inline int grid_for(long long n) {
 }  // namespace
 
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s) {
-    StepFn f = pick_step(a.L.ndim, a.L.r, st, mode);
+    StepFn f = pick_step(a.L.ndim, a.L.r, st, mode, a.tile_w4);
     if (!f) return hipErrorInvalidValue;
     const int tiles = a.ntx * a.nty * a.ntz;
     const int blocks = tiles + a.nsamp_blocks;
@@ -1001,8 +1006,8 @@ hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
-int step_blocks_per_cu(int ndim, int r, Store st, int mode) {
-    StepFn f = pick_step(ndim, r, st, mode);
+int step_blocks_per_cu(int ndim, int r, Store st, int mode, int tw4) {
+    StepFn f = pick_step(ndim, r, st, mode, tw4);
     if (!f) return 0;
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(f), kBlock, 0) !=

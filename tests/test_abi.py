@@ -42,6 +42,7 @@ def _desc(**kw):
     d.space_order = kw.get("so", 8)
     d.nbl = kw.get("nbl", 10)
     d.storage = kw.get("storage", 0)
+    d.tile_x = kw.get("tile_x", 0)
     return d
 
 
@@ -59,11 +60,15 @@ def test_workspace_bytes_grow_with_grid(lib):
     assert b1 >= 4 * 4 * (84 * 68 * 52)
     rc3, b3 = _bytes(lib, _desc(shape=(64, 48, 32), storage=_lib.FD_STORE_BF16))
     assert rc3 == 0 and b3 < b1
+    # either 3D tile shape is a valid description (their source tables differ)
+    for tx in (32, 64):
+        rc4, b4 = _bytes(lib, _desc(shape=(64, 48, 32), tile_x=tx))
+        assert rc4 == 0 and b4 > 0
 
 
 @pytest.mark.parametrize("bad", [
     dict(ndim=4), dict(so=3), dict(so=18), dict(so=0), dict(nbl=-1), dict(shape=(1, 8, 8)),
-    dict(storage=7),
+    dict(storage=7), dict(tile_x=48), dict(tile_x=-32),
 ])
 def test_invalid_descriptors_rejected(lib, bad):
     rc, _ = _bytes(lib, _desc(**bad))

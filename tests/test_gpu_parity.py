@@ -40,17 +40,19 @@ def test_acoustic2d_101_workload():
 
 @pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16])
 @pytest.mark.parametrize("zchunk", [0, 7])
-def test_3d_every_space_order(so, zchunk):
-    """70x37x29 + 5-point layer: 2 x tiles (ragged), 3 y tiles (ragged),
-    z chunks of 7 or automatic; 3 sources, 9 receivers, 60 steps."""
+@pytest.mark.parametrize("tile_x", [64, 32])
+def test_3d_every_space_order(so, zchunk, tile_x):
+    """70x37x29 + 5-point layer (80 x 47 x 39 padded): 64 x 16 tiles give 2
+    x tiles and 3 y tiles, 32 x 32 tiles 3 and 2, all ragged; z chunks of 7
+    or automatic; 3 sources, 9 receivers, 60 steps."""
     need_gpu()
     c = case((70, 37, 29), so, 5, 60, seed=so, nsrc=3, nrec=9)
     want, u_nt, _, _ = oracle_forward(c)
-    g = gpu_grid(c, zchunk=zchunk)
+    g = gpu_grid(c, zchunk=zchunk, tile_x=tile_x)
     _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
     e_rec = rel_l2(rec.cpu().numpy(), want)
     e_u = rel_l2(state[0].cpu().numpy(), u_nt)
-    _print("3d so=%d zchunk=%d" % (so, zchunk), rec=e_rec, field=e_u)
+    _print("3d so=%d zchunk=%d tile_x=%d" % (so, zchunk, tile_x), rec=e_rec, field=e_u)
     assert e_rec <= TOL and e_u <= TOL
 
 

@@ -1,0 +1,98 @@
+"""The two 3D workgroup tile shapes (64 x 16 and 32 x 32 points in xy).
+
+Each point's update is the same sequence of float32 operations whatever
+tile computes it, and source terms are summed per grid point in a fixed
+order, so every result must be bitwise the same under either shape: traces,
+final fields, adjoint source traces and gradients, for every storage type.
+The oracle parity of the 32 x 32 shape on its own is covered by the 3D
+parity tests, which run both shapes.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import case, gpu_forward, gpu_grid, need_gpu, oracle_forward, rel_l2, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(c, **kw):
+    out = []
+    for tx in (64, 32):
+        g = gpu_grid(c, tile_x=tx, **kw)
+        assert g.tile == ((64, 16) if tx == 64 else (32, 32))
+        _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
+        out.append((rec, state))
+        g.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("so", [4, 8, 16])
+def test_forward_bitwise_across_tile_shapes(storage, so):
+    """90 x 70 x 33 + 6: ragged last tiles in x and y under both shapes,
+    4 sources, 13 receivers, 50 steps."""
+    need_gpu()
+    c = case((90, 70, 33), so, 6, 50, seed=40 + so, nsrc=4, nrec=13)
+    (r1, s1), (r2, s2) = _both(c, storage=storage)
+    print("tiles %s so=%d: traces equal %d, field equal %d" % (storage, so, int(torch.equal(r1, r2)),
+                                                               int(torch.equal(s1[0], s2[0]))), flush=True)
+    assert torch.equal(r1, r2)
+    assert torch.equal(s1[0], s2[0]) and torch.equal(s1[1], s2[1])
+
+
+def test_narrow_tiles_against_oracle_many_sources():
+    """Sources spread over several 32 x 32 tiles and planes (scatter with the
+    narrow row stride), windowed-sinc nodes shared between tiles."""
+    need_gpu()
+    c = case((75, 69, 28), 8, 4, 40, seed=77, nsrc=12, nrec=9)
+    c["sinc"] = 3
+    want, u_nt, _, _ = oracle_forward(c)
+    g = gpu_grid(c, tile_x=32)
+    _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
+    e_rec = rel_l2(rec.cpu().numpy(), want)
+    e_u = rel_l2(state[0].cpu().numpy(), u_nt)
+    print("32x32 tiles, sinc 3, 12 sources: traces %.3e field %.3e" % (e_rec, e_u), flush=True)
+    assert e_rec <= 1e-5 and e_u <= 1e-5
+
+
+def test_adjoint_and_gradient_bitwise_across_tile_shapes():
+    """fd_adjoint and fd_gradient (recomputing schedule, and every bracket
+    resident) give bitwise the same outputs under either tile shape."""
+    need_gpu()
+    c = case((60, 45, 30), 8, 5, 70, seed=8, nsrc=2, nrec=11)
+    dev = torch.device("cuda:0")
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    rng = np.random.default_rng(4)
+    obs = torch.from_numpy(rng.standard_normal((c["nt"], len(c["rec"]))).astype(np.float32) * 1e-3).to(dev)
+    outs = []
+    for tx in (64, 32):
+        g = gpu_grid(c, tile_x=tx)
+        adj = g.adjoint(c["src"], c["rec"], obs, c["dt"])
+        grads = [g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=K) for K in (9, c["nt"])]
+        torch.cuda.synchronize()
+        outs.append((adj, grads))
+        g.close()
+    (a1, g1), (a2, g2) = outs
+    assert torch.equal(a1, a2)
+    for x, y in zip(g1, g2):
+        assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1]) and torch.equal(x[2], y[2])
+    print("adjoint and gradients bitwise equal across tile shapes", flush=True)
+
+
+@pytest.mark.parametrize("shape,so,want", [
+    ((200, 200, 40), 8, (64, 16)),     # so <= 8: always 64 x 16
+    ((200, 200, 40), 12, (32, 32)),    # so 10, 12, padded x 280 = 4.375 x 64: ragged rows
+    ((240, 200, 40), 12, (64, 16)),    # padded x 320: whole 64-point rows
+    ((256, 256, 40), 12, (64, 16)),    # padded 336: 87.5 % vs 91 % of lanes used, too close
+    ((240, 200, 40), 16, (32, 32)),    # so >= 14: always 32 x 32
+    ((31, 20), 16, (64, 64)),          # 2D: 64 x-points by 64 z-rows
+])
+def test_automatic_tile_choice(shape, so, want):
+    need_gpu()
+    dev = torch.device("cuda:0")
+    from paper_1906_10811_amd import Grid
+    v = torch.full(tuple(reversed(shape)), 2000.0, device=dev)
+    g = Grid(shape, (10.0,) * len(shape), v, space_order=so, nbl=40)
+    print("padded", g.padded, "so", so, "tile", g.tile, "zchunk", g.zchunk, flush=True)
+    assert g.tile == want
+    g.close()
