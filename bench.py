@@ -324,7 +324,7 @@ def bench_sinc(torch, dev, stream):
     return res
 
 
-def bench_serving(torch, n=24, budget_gib=8.0, slots=6):
+def bench_serving(torch, n=64, budget_gib=8.0, slots=6):
     """Shot server: n requests with Poisson arrivals at 0.8x the measured
     one-at-a-time capacity; reports shots/s, p50/p99 latency and the
     throughput in Gpts/s, against plain one-at-a-time FP32 stepping."""

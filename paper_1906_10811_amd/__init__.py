@@ -11,6 +11,7 @@ point raises -- there is no CPU fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -206,7 +207,12 @@ class Grid:
             K = int(binomial_slots)
         nbytes = ctypes.c_size_t()
         _lib.check(lib.fd_gradient_workspace_bytes(self._h, nt, sh.nrec, K, flags, ctypes.byref(nbytes)))
-        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        # The workspace (up to the whole forward history) is allocated on the
+        # stream the work runs on, so that torch's caching allocator hands the
+        # same block to the next gradient on that stream instead of reserving
+        # a second one (a block allocated on another stream is not reused).
+        with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+            ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
         aligned = (ws.data_ptr() + 255) // 256 * 256
         misfit = torch.empty(1, dtype=torch.float64, device=self.device)
         grad = torch.empty(self.array_shape, dtype=torch.float64, device=self.device)

@@ -374,7 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     // dt^2 v^2 and u^{n-1}.  Three register sets rotate so that the loads of
     // plane z+2 are in flight while plane z is computed (two planes ahead);
     // the loop is unrolled by three so the rotation needs no register moves,
-    // which would otherwise wait for the loads they move.
+    // which would otherwise wait for the loads they move.  (A fourth set,
+    // three planes ahead, measured 1-2.5 % slower.)
     using Raw = typename E::Raw;
     struct PlaneRegs {
         Raw front, mv;

@@ -230,6 +230,31 @@ def test_gradient_resident_brackets_equal_recompute():
     assert torch.equal(r1, r2) and torch.equal(m1, m2) and torch.equal(g1, g2) and torch.equal(a1, a2)
 
 
+def test_gradient_on_a_side_stream_reuses_its_workspace():
+    """fd_gradient enqueued on a caller's stream: the result equals the
+    current-stream result, and a later call on that stream reuses the
+    workspace block whichever stream is current at the call (a block that
+    belongs to another stream would not be handed out again)."""
+    need_gpu()
+    c, vp, sig, d_obs = _gradient_case()
+    g = gpu_grid(c)
+    dev = torch.device("cuda:0")
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    obs = torch.from_numpy(d_obs).to(dev)
+    m0, g0, _, _ = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=c["nt"])
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    m1, g1, _, _ = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=c["nt"], stream=side)
+    torch.cuda.synchronize()
+    reserved = torch.cuda.memory_reserved()
+    with torch.cuda.stream(side):
+        m2, g2, _, _ = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=c["nt"], stream=side)
+    torch.cuda.synchronize()
+    _print("side stream", reserved_before=reserved, reserved_after=torch.cuda.memory_reserved())
+    assert torch.cuda.memory_reserved() == reserved
+    assert torch.equal(m0, m1) and torch.equal(g0, g1) and torch.equal(m1, m2) and torch.equal(g1, g2)
+
+
 @pytest.mark.parametrize("slots", [0, 3, 9])
 def test_gradient_binomial_schedule(slots):
     """The binomial checkpoint schedule (snapshot slots 0, 3, 9) reproduces
