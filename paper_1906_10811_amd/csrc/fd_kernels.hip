@@ -25,6 +25,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fd {
 namespace {
 
@@ -190,13 +192,8 @@ __device__ inline float update_point(float c, float m, float p, float lap, float
     return alpha * __builtin_fmaf(p, lap + src, t);
 }
 
-// One radius-j term of the Laplacian at a point: the weights times the sums
-// of the two neighbours at distance j along each axis (lap_term2: 2D).
-__device__ inline float lap_term3(float wx, float xs, float wy, float ys, float wz, float zs) {
-    float acc = wx * xs;
-    acc = __builtin_fmaf(wy, ys, acc);
-    return __builtin_fmaf(wz, zs, acc);
-}
+// One radius-j term of the 2D Laplacian at a point: the weights times the
+// sums of the two neighbours at distance j along each axis.
 __device__ inline float lap_term2(float wx, float xs, float wz, float zs) {
     return __builtin_fmaf(wz, zs, wx * xs);
 }
@@ -246,6 +243,15 @@ __device__ inline void grad_epilogue(const Imaging &img, long long off, int nval
 }
 
 // ------------------------------------------------------------------ 3D step
+// f(integral_constant<I>) for I = B .. E-1, unrolled at compile time.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 // TW float4 columns per tile row: 16 (64 x 16 tiles) or 8 (32 x 32 tiles).
 template <int R, Store S, int MODE, int TW>
 __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
@@ -354,7 +360,15 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         const int xi = min(x + i, L.nx - 1);
         sxy[i] = active ? a.damp[xi] + a.damp[L.nx + y] : 0.f;
     }
-    float4 q[2 * R + 1];
+    // The z queue: logical entry k (0 = plane z-R .. 2R = plane z+R) of the
+    // body with rotation ROT lives in q[(k + ROT) % NQ].  When 3 divides NQ
+    // the plane loop is unrolled NQ times and the rotation advances one per
+    // plane, so the queue never moves; otherwise ROT stays 0 and the entries
+    // shift down after each plane.
+    constexpr int NQ = 2 * R + 1;
+    constexpr bool kRot = NQ % 3 == 0 && MODE != kImage;   // (imaging: registers for 3 workgroups/CU)
+    constexpr int UNR = kRot ? NQ : 3;
+    float4 q[NQ];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) q[k] = E::ld4(U + base + (long long)(zs + dir * (k - R)) * plane);
 
@@ -383,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         Raw hv[HPT];      // halo of plane z+R
         float4 br, gp;    // imaging step: bracket and partial gradient of plane z
     };
-    auto issue = [&](PlaneRegs &r, int st) {
+    auto issue = [&](PlaneRegs &r, int st) __attribute__((always_inline)) {
         st = min(st, len - 1);   // past the chunk: a harmless in-bounds reload
         const long long zo = (long long)(zs + dir * st) * plane;
         const long long fo = zo + (long long)(dir * R) * plane;   // the queue front, R planes ahead
@@ -397,11 +411,13 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             r.gp = ld4nt_f32(a.img.gpart + base + zo);
         }
     };
-    auto body = [&](int st, const PlaneRegs &cur, PlaneRegs &ahead) {
+    auto body = [&](auto rot, int st, const PlaneRegs &cur, PlaneRegs &ahead) __attribute__((always_inline)) {
+        constexpr int ROT = kRot ? decltype(rot)::value : 0;
+#define QQ(k) q[((k) + ROT) % NQ]
         const int z = zs + dir * st;
         float4 *buf = lds[st & 1];
-        q[2 * R] = E::cvt(cur.front);
-        buf[(R + ty) * W4 + HX4 + tx] = q[R];
+        QQ(2 * R) = E::cvt(cur.front);
+        buf[(R + ty) * W4 + HX4 + tx] = QQ(R);
         // park the halo of plane z+R (fetched with the front of the same
         // plane) and stage the halo of plane z parked R planes ago
         float4 *ring_w = ring + ((st + R) % kRing) * NH + lane;
@@ -433,22 +449,27 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             const float4 *row = buf + (R + ty) * W4 + HX4 + tx;
 #pragma unroll
             for (int c = -HX4; c <= HX4; ++c) {
-                const float4 v = (c == 0) ? q[R] : row[c];
+                const float4 v = (c == 0) ? QQ(R) : row[c];
                 xs[4 * (c + HX4) + 0] = v.x;
                 xs[4 * (c + HX4) + 1] = v.y;
                 xs[4 * (c + HX4) + 2] = v.z;
                 xs[4 * (c + HX4) + 3] = v.w;
             }
+            // per radius j one fused multiply-add per axis on the sum of the
+            // two neighbours, the centre term last (the sum then builds up
+            // from the small neighbour terms before the large centre one
+            // cancels it)
             float lap[4];
 #pragma unroll
             for (int j = 1; j <= R; ++j) {
                 const float4 yp = row[j * W4], ym = row[-j * W4];
-                const float4 zp = q[R + j], zm = q[R - j];
+                const float4 zp = QQ(R + j), zm = QQ(R - j);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float t = lap_term3(a.wx[j], xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j], a.wy[j],
-                                              comp(yp, i) + comp(ym, i), a.wz[j], comp(zp, i) + comp(zm, i));
-                    lap[i] = j == 1 ? t : lap[i] + t;
+                    const float xsum = xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j];
+                    lap[i] = j == 1 ? a.wx[1] * xsum : __builtin_fmaf(a.wx[j], xsum, lap[i]);
+                    lap[i] = __builtin_fmaf(a.wy[j], comp(yp, i) + comp(ym, i), lap[i]);
+                    lap[i] = __builtin_fmaf(a.wz[j], comp(zp, i) + comp(zm, i), lap[i]);
                 }
             }
 #pragma unroll
@@ -458,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
             float un[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                un[i] = update_point(comp(q[R], i), comp(mvf, i), comp(cur.pv, i), lap[i], src[i],
+                un[i] = update_point(comp(QQ(R), i), comp(mvf, i), comp(cur.pv, i), lap[i], src[i],
                                      sxy[i] + sz);
             const long long off = base + (long long)z * plane;
             const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
@@ -479,27 +500,41 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
                 float sv[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) sv[i] = sxy[i] + sz;
-                grad_epilogue<MODE>(a.img, off, nvalid, un, q[R], mvf, sv);
+                grad_epilogue<MODE>(a.img, off, nvalid, un, QQ(R), mvf, sv);
             } else if constexpr (MODE == kImage) {
                 image_accumulate(a.img.gpart + off, nvalid, un, cur.br, cur.gp);
             }
         }
+        if constexpr (!kRot) {
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k) q[k] = q[k + 1];
+            for (int k = 0; k < 2 * R; ++k) q[k] = q[k + 1];
+        }
+#undef QQ
     };
 
     __syncthreads();   // staged tables and the cleared source tile, before the first plane
     PlaneRegs s0, s1, s2;
+    auto set = [&](auto I) -> PlaneRegs & {   // register set I mod 3
+        constexpr int k = decltype(I)::value % 3;
+        if constexpr (k == 0) return s0;
+        else if constexpr (k == 1) return s1;
+        else return s2;
+    };
     issue(s0, 0);
     issue(s1, 1);
     int st = 0;
-    for (; st + 3 <= len; st += 3) {
-        body(st, s0, s2);
-        body(st + 1, s1, s0);
-        body(st + 2, s2, s1);
-    }
-    if (st < len) body(st, s0, s2);
-    if (st + 1 < len) body(st + 1, s1, s0);
+    // body i of an unrolled group computes from set i mod 3 and issues into
+    // set (i + 2) mod 3; UNR is a multiple of 3, so each group starts from
+    // the same sets (and, when the queue rotates, from rotation 0)
+    for (; st + UNR <= len; st += UNR)
+        static_for<0, UNR>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            body(I, st + i, set(I), set(std::integral_constant<int, i + 2>{}));
+        });
+    static_for<0, UNR - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if (st + i < len) body(I, st + i, set(I), set(std::integral_constant<int, i + 2>{}));
+    });
 }
 
 // ------------------------------------------------------------------ 2D step

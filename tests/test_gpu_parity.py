@@ -250,8 +250,12 @@ def test_gradient_on_a_side_stream_reuses_its_workspace():
     with torch.cuda.stream(side):
         m2, g2, _, _ = g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=c["nt"], stream=side)
     torch.cuda.synchronize()
-    _print("side stream", reserved_before=reserved, reserved_after=torch.cuda.memory_reserved())
-    assert torch.cuda.memory_reserved() == reserved
+    ws = g.gradient_workspace_bytes(c["nt"], len(c["rec"]), checkpoint_every=c["nt"])
+    grown = torch.cuda.memory_reserved() - reserved
+    _print("side stream", workspace=ws, reserved_growth=grown)
+    # the small outputs may open a new pool segment on the side stream; a
+    # second workspace would add at least its own size
+    assert grown < ws // 2
     assert torch.equal(m0, m1) and torch.equal(g0, g1) and torch.equal(m1, m2) and torch.equal(g1, g2)
 
 
