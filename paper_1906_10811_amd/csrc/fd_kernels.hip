@@ -362,11 +362,14 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     }
     // The z queue: logical entry k (0 = plane z-R .. 2R = plane z+R) of the
     // body with rotation ROT lives in q[(k + ROT) % NQ].  When 3 divides NQ
-    // the plane loop is unrolled NQ times and the rotation advances one per
-    // plane, so the queue never moves; otherwise ROT stays 0 and the entries
-    // shift down after each plane.
+    // the plane loop can be unrolled NQ times with the rotation advancing
+    // one per plane, so the queue never moves; otherwise ROT stays 0 and the
+    // entries shift down after each plane.  Measured: at so 14 the rotating
+    // queue is 3.7 % faster; at so 8 its nine-fold loop fetched 2.6 % more
+    // bytes from HBM and ran 1.7 % slower (the step is HBM-bound there), and
+    // in the imaging mode it needs registers that cost a workgroup per CU.
     constexpr int NQ = 2 * R + 1;
-    constexpr bool kRot = NQ % 3 == 0 && MODE != kImage;   // (imaging: registers for 3 workgroups/CU)
+    constexpr bool kRot = NQ % 3 == 0 && MODE != kImage && R != 4;
     constexpr int UNR = kRot ? NQ : 3;
     float4 q[NQ];
 #pragma unroll
