@@ -184,13 +184,17 @@ def bench_gradient(torch, dev, stream):
         e1.record(stream)
     torch.cuda.synchronize()
     secs = e0.elapsed_time(e1) / 1000.0 / reps
-    # algorithmic bytes per point and time step: forward 16, recompute 16 +
-    # bracket write 4, adjoint 16 + bracket read 4 + float32 partial-sum
+    # algorithmic bytes per point and time step: forward 16 (20 with the
+    # bracket write in the last segment), recompute of the other segments
+    # 16 + bracket write 4, adjoint 16 + bracket read 4 + float32 partial-sum
     # read-modify-write 8, the fold into the float64 gradient (read 4, RMW 16,
     # clear 4) every 32 adjoint steps, and two field copies (read + write)
-    # per checkpoint and per segment restore
+    # per checkpoint and per segment restore (none for the last segment)
     K = w["checkpoint_every"]
-    b_alg = 64.0 + 24.0 / 32 + 32.0 / K
+    nt = w["nt"]
+    nseg = -(-nt // K)
+    last = nt - (nseg - 1) * K
+    b_alg = 16.0 + 4.0 * last / nt + 20.0 * (nt - last) / nt + 28.0 + 24.0 / 32 + 2 * 16.0 * (nseg - 1) / nt
     gpts = g.padded_points * w["nt"] / secs / 1e9
     out = dict(workload="gradient3d_200", gpts=gpts, ms=secs * 1000.0, misfit=float(mis.item()),
                checkpoint_every=K, b_alg_per_pt=b_alg, achieved_gbs=gpts * b_alg,

@@ -191,7 +191,8 @@ int fd_adjoint(fd_grid *grid, const fd_shot *shot, int nt, double dt,
                                       the reverse sweep follows fd_checkpoint_schedule */
 
 /* Device workspace for fd_gradient.  Default: checkpoints of (u^c, u^{c-1})
- * every checkpoint_every steps and checkpoint_every bracket fields of the
+ * every checkpoint_every steps except the last segment's (ceil(nt /
+ * checkpoint_every) - 1 pairs) and checkpoint_every bracket fields of the
  * segment recompute; with checkpoint_every >= nt, nt bracket fields and no
  * checkpoint (the forward pass keeps every bracket, nothing is recomputed).
  * FD_GRAD_BINOMIAL: checkpoint_every + 1 snapshots and two scratch fields.
@@ -234,7 +235,8 @@ int fd_checkpoint_schedule(int nt, int slots, fd_ckpt_action *actions, int capac
  *   g_m = - sum_n lambda^n [(u^{n+1} - 2u^n + u^{n-1}) + (sigma dt/2)(u^{n+1} - u^{n-1})]
  * with lambda the adjoint field driven by the residual.  The bracket of each
  * level comes from a forward step that also writes it: recomputed from
- * checkpoints, or kept from the forward pass when checkpoint_every >= nt.
+ * checkpoints, or kept from the forward pass (the last segment's levels,
+ * and every level when checkpoint_every >= nt).
  * Products are summed in float32 over 32 adjoint steps, then added to the
  * float64 gradient.  d_obs_dev: device float32 [nt][nrec]
  * (the residual itself when flags has FD_GRAD_RESIDUAL_GIVEN).

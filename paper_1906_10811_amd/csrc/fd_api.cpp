@@ -932,14 +932,17 @@ namespace {
 // residual.
 struct GradPlan {
     size_t ckpt, rot, br, grad, gpart, rec, resid, total;
-    int ncp, K, nbr;
+    int ncp, nseg, K, nbr;   // checkpoint pairs (binomial: snapshot slots + 1), fixed-interval segments
     bool binomial;
 };
 GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K, int flags) {
     GradPlan p{};
     p.K = K;
     p.binomial = (flags & FD_GRAD_BINOMIAL) != 0;
-    p.ncp = p.binomial ? std::min(K, nt) + 1 : (K >= nt ? 0 : (nt + K - 1) / K);
+    // fixed interval: segments of K steps; no checkpoint is stored for the
+    // last segment, whose brackets the forward pass writes directly
+    p.nseg = p.binomial ? 0 : (K >= nt ? 1 : (nt + K - 1) / K);
+    p.ncp = p.binomial ? std::min(K, nt) + 1 : p.nseg - 1;
     p.nbr = p.binomial ? 2 : std::min(K, nt);   // binomial: output field + bracket
     const size_t fb = g->wp.field_bytes;
     size_t o = 0;
@@ -1071,26 +1074,43 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
         for (int k = nt; k >= 1; --k)
             if ((rc = adjoint_step(k, br[k - 1]))) return rc;
     } else if (!gp.binomial) {
-        // 1. forward with checkpoints of (u^c, u^{c-1}) every K steps
+        // 1. forward with checkpoints of (u^c, u^{c-1}) every K steps.  The
+        //    steps of the last segment write their imaging brackets as they
+        //    go: the sweep below would otherwise recompute exactly these
+        //    steps first (the bracket mode's u is bitwise the plain mode's).
+        const int clast = (gp.nseg - 1) * K;
         HIPCHK(launch_zero_field(L, g->uA, g->st, s));
         HIPCHK(launch_zero_field(L, g->uB, g->st, s));
-        if ((rc = fdi_forward_steps(g, sh, nt, 0, nt, recb, ck.data(), K, s))) return rc;
+        if ((rc = fdi_forward_steps(g, sh, nt, 0, clast, recb, ck.data(), K, s))) return rc;
+        {
+            void *A = (clast % 2 == 0) ? g->uA : g->uB;   // u^n, u^{n-1}, as the chunked forward leaves them
+            void *B = (clast % 2 == 0) ? g->uB : g->uA;
+            for (int n = clast; n < nt; ++n) {
+                if ((rc = bracket_step(n, A, B, B, br[n - clast], recb + (size_t)(n - 1) * sh->nrec))) return rc;
+                std::swap(A, B);
+            }
+            Sample sm = make_sample(g, 1, sh->nrec, recb + (size_t)(nt - 1) * sh->nrec, 1.f);
+            HIPCHK(launch_sample(sm, A, g->st, s));
+        }
         // 2. residual and misfit (FP64)
         HIPCHK(launch_misfit(recb, d_obs, nres, given, resid, g->partials, kNPart, misfit, s));
-        // 3. adjoint sweep over segments, last to first.  Each segment is
-        //    recomputed from its checkpoint, writing the imaging bracket of
-        //    every time level; the adjoint steps read one bracket per point.
+        // 3. adjoint sweep over segments, last to first.  Each earlier
+        //    segment is recomputed from its checkpoint, writing the imaging
+        //    bracket of every time level; the adjoint steps read one bracket
+        //    per point.
         HIPCHK(launch_zero_field(L, g->uA, g->st, s));
         HIPCHK(launch_zero_field(L, g->uB, g->st, s));
-        for (int seg = gp.ncp - 1; seg >= 0; --seg) {
+        for (int seg = gp.nseg - 1; seg >= 0; --seg) {
             const int c = seg * K;
             const int e = std::min(c + K, nt);
-            HIPCHK(hipMemcpyAsync(rotA, ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(rotB, ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
-            void *A = rotA, *B = rotB;   // u^n, u^{n-1}
-            for (int n = c; n < e; ++n) {
-                if ((rc = bracket_step(n, A, B, B, br[n - c], nullptr))) return rc;
-                std::swap(A, B);
+            if (c != clast) {
+                HIPCHK(hipMemcpyAsync(rotA, ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(rotB, ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
+                void *A = rotA, *B = rotB;   // u^n, u^{n-1}
+                for (int n = c; n < e; ++n) {
+                    if ((rc = bracket_step(n, A, B, B, br[n - c], nullptr))) return rc;
+                    std::swap(A, B);
+                }
             }
             for (int k = e; k >= c + 1; --k)
                 if ((rc = adjoint_step(k, br[k - 1 - c]))) return rc;
