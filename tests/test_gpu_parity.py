@@ -189,6 +189,35 @@ def test_gradient_parity(K):
     assert eg <= 1e-4
 
 
+def test_gradient_parity_so14():
+    """Space order 14, where the bracket mode runs the z queue that rotates
+    by index (2r + 1 = 15 planes, the plane loop unrolled 15 times): fixed
+    interval 13 (ragged last segment) and every bracket resident, against
+    the oracle's gradient; the two schedules agree bitwise."""
+    need_gpu()
+    c = case((30, 27, 23), 14, 4, 120, seed=21, nsrc=1, nrec=6)
+    og = c["og"]
+    vp = oracle.pad_velocity(og, c["v"])
+    sig = oracle.damping(og, oracle.sigma_max_default(og, float(vp.max())))
+    v_true = vp.copy()
+    v_true[8:20, 8:22, 8:26] *= 1.1
+    wav = c["wav"].astype(np.float64)
+    d_obs, *_ = oracle.forward(og, v_true, sig, c["dt"], c["nt"], c["src"], wav, c["rec"])
+    J, grad, _ = oracle.gradient(og, vp, sig, c["dt"], c["nt"], c["src"], wav, c["rec"], d_obs)
+    g = gpu_grid(c)
+    dev = torch.device("cuda:0")
+    obs = torch.from_numpy(d_obs.astype(np.float32)).to(dev)
+    w = torch.from_numpy(c["wav"]).to(dev)
+    m1, g1, _, _ = g.gradient(c["src"], w, c["rec"], obs, c["dt"], checkpoint_every=13)
+    m2, g2, _, _ = g.gradient(c["src"], w, c["rec"], obs, c["dt"], checkpoint_every=c["nt"])
+    torch.cuda.synchronize()
+    eJ = abs(float(m1.item()) - J) / J
+    eg = rel_l2(g1.cpu().numpy(), grad)
+    _print("gradient so 14", eJ=eJ, grad=eg, schedules_bitwise=int(torch.equal(g1, g2)))
+    assert eJ <= 1e-4 and eg <= 1e-4
+    assert torch.equal(m1, m2) and torch.equal(g1, g2)
+
+
 @pytest.mark.parametrize("K", [9, 1000])
 def test_gradient_parity_2d(K):
     """The 2D kernel's bracket and imaging epilogues: fd_gradient on a 2D
