@@ -99,8 +99,10 @@ typedef struct fd_grid_desc {
                               tables, about 36 B per node, scale with max_src and
                               max_rec: 3D radius 8 with 4096 receivers is 0.6 GB) */
     double sinc_beta;      /* Kaiser shape b; <= 0 selects pi * sinc_radius / 2 */
-    int tile_x;            /* 3D workgroup tile in x points: 64 (64 x 16 xy tiles) or 32
-                              (32 x 32); 0 selects automatically; ignored in 2D */
+    int tile_x;            /* 3D workgroup tiles: 64 (64 x 16 xy tiles), 32 (32 x 32), 96
+                              (64 x 16, and 32 x 32 for a last x column of at most 32
+                              points; 64 x 16 alone when there is none), 0 selects
+                              automatically; ignored in 2D */
 } fd_grid_desc;
 
 /* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
@@ -131,6 +133,8 @@ typedef struct fd_grid_info {
     size_t field_bytes;    /* one wavefield buffer as laid out on the device */
     int tile[2];           /* 3D: xy tile of the step workgroups in points (64 x 16 or
                               32 x 32); 2D: (64, 64), x points and z rows */
+    int tile_strip;        /* 3D: width of the last x column when it runs 32 x 32 tiles
+                              beside 64 x 16 ones, else 0 */
     int zchunk;            /* 3D: z planes per workgroup of a plain step; 2D: 64 */
 } fd_grid_info;
 

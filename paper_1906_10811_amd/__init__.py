@@ -100,6 +100,7 @@ class Grid:
         self.damp_max = info.damp_max
         self.field_bytes = int(info.field_bytes)
         self.tile = (int(info.tile[0]), int(info.tile[1]))
+        self.tile_strip = int(info.tile_strip)
         self.zchunk = int(info.zchunk)
 
     @property

@@ -87,6 +87,7 @@ class GridInfo(ctypes.Structure):
         ("damp_max", ctypes.c_double),
         ("field_bytes", ctypes.c_size_t),
         ("tile", ctypes.c_int * 2),
+        ("tile_strip", ctypes.c_int),
         ("zchunk", ctypes.c_int),
     ]
 

@@ -109,8 +109,8 @@ bool fdi_check_desc(const fd_grid_desc *d) {
     if (d->storage < 0 || d->storage > 2) return fdi_fail(FD_ERR_ARG, "storage"), false;
     if (d->amp_scale < 0.f || !std::isfinite(d->amp_scale)) return fdi_fail(FD_ERR_ARG, "amp_scale"), false;
     if (d->max_src < 0 || d->max_rec < 0 || d->zchunk < 0) return fdi_fail(FD_ERR_ARG, "capacities"), false;
-    if (d->tile_x != 0 && d->tile_x != 32 && d->tile_x != 64)
-        return fdi_fail(FD_ERR_ARG, "tile_x must be 0, 32 or 64"), false;
+    if (d->tile_x != 0 && d->tile_x != 32 && d->tile_x != 64 && d->tile_x != 96)
+        return fdi_fail(FD_ERR_ARG, "tile_x must be 0, 32, 64 or 96"), false;
     if (d->sinc_radius < 0 || d->sinc_radius > kMaxSincR)
         return fdi_fail(FD_ERR_ARG, "sinc_radius must be 0..%d", kMaxSincR), false;
     if (!std::isfinite(d->sinc_beta)) return fdi_fail(FD_ERR_ARG, "sinc_beta"), false;
@@ -194,33 +194,59 @@ int sparse_nodes(const fd_grid_desc *d) {
 // (by 3-11 %), 32 x 32 from so 14 on (by 4-16 %, 25 % in 16-bit at 280^3);
 // at so 10 and 12 the 32 x 32 shape wins only where 64-point rows leave many
 // lanes idle (280 = 4.375 x 64: +2 %, 16-bit +4-6 %; 336 = 5.25 x 64: -3 %).
+// A ragged last x column of at most 32 points fills a 64 x 16 tile's lanes
+// to half or less; the mixed shape gives that column 32 x 32 tiles instead.
+// Measured, float32 (against 64 x 16 everywhere): 280^3 +7 % at so 4, +9 %
+// at so 8, +10 % at so 12 (also 10 % above 32 x 32 tiles there), 336^3
+// +1 %, 592^3 +2.5 %.  With 16-bit fields a 32-point row is half a cache
+// line and the mixed shape lost 7-10 %, so 16-bit grids keep 64 x 16.
 constexpr double kTileNarrowGain = 0.06;   // lane-use margin that selects 32 x 32 at so 10, 12
 
-int tile_w4(const fd_grid_desc *d, const Layout &L) {
-    if (L.ndim != 3 || d->tile_x == 64) return 16;
+bool mixed_fits(const Layout &L) { return L.nx > 64 && L.nx % 64 != 0 && L.nx % 64 <= 32; }
+
+// Tile shape code of a grid (16, 8 or kShapeMixed; 2D grids: 16).
+int tile_shape(const fd_grid_desc *d, const Layout &L) {
+    if (L.ndim != 3) return 16;
+    if (d->tile_x == 64) return 16;
     if (d->tile_x == 32) return 8;
-    if (L.r >= 7) return 8;
-    if (L.r <= 4) return 16;
+    if (L.r >= 7) return 8;   // no mixed kernel at so 14, 16
+    if (d->tile_x == 96) return mixed_fits(L) ? kShapeMixed : 16;
+    if (d->storage == FD_STORE_F32 && mixed_fits(L)) return kShapeMixed;
     auto used = [&](int tw4) {   // fraction of tile lanes that hold a grid point
         const double tx = tile3_x(tw4), ty = tile3_y(tw4);
         return (double)L.nx * L.ny / (std::ceil(L.nx / tx) * tx * std::ceil(L.ny / ty) * ty);
     };
-    return used(8) > used(16) + kTileNarrowGain ? 8 : 16;
+    return L.r >= 5 && used(8) > used(16) + kTileNarrowGain ? 8 : 16;
 }
+
+struct TileGrid {
+    int ntx, nty, nstrip;   // 64 x 16 (or single-shape) tiles per axis; 32 x 32 tiles of the last column
+    int tiles() const { return ntx * nty + nstrip; }
+};
 
 // Tiles of the step kernels' xy (3D) or x (2D) decomposition; the injection
 // tables keep one plane-pointer row per tile.
-int xy_tiles(const Layout &L, int tw4) {
-    const int ntx = L.ndim == 3 ? (L.nx + tile3_x(tw4) - 1) / tile3_x(tw4) : (L.nx + kTileX - 1) / kTileX;
-    const int nty = L.ndim == 3 ? (L.ny + tile3_y(tw4) - 1) / tile3_y(tw4) : 1;
-    return ntx * nty;
+TileGrid tile_grid(const Layout &L, int shape) {
+    TileGrid t{};
+    if (L.ndim != 3) {
+        t.ntx = (L.nx + kTileX - 1) / kTileX;
+        t.nty = 1;
+    } else if (shape == kShapeMixed) {
+        t.ntx = L.nx / 64;
+        t.nty = (L.ny + 15) / 16;
+        t.nstrip = (L.ny + 31) / 32;
+    } else {
+        t.ntx = (L.nx + tile3_x(shape) - 1) / tile3_x(shape);
+        t.nty = (L.ny + tile3_y(shape) - 1) / tile3_y(shape);
+    }
+    return t;
 }
 
 WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     WsPlan w{};
     const size_t esz = d->storage == FD_STORE_F32 ? 4 : 2;
     const int nc = sparse_nodes(d);
-    const size_t nptr = (size_t)xy_tiles(L, tile_w4(d, L)) * (L.nz + 1);
+    const size_t nptr = (size_t)tile_grid(L, tile_shape(d, L)).tiles() * (L.nz + 1);
     w.cap_src = d->max_src ? d->max_src : 64;
     w.cap_rec = d->max_rec ? d->max_rec : 4096;
     w.field_bytes = align_up((size_t)L.elems * esz, 256);
@@ -276,7 +302,8 @@ struct fd_grid {
     hipEvent_t stage_ev;
     bool stage_pending;
     int ntx, nty;
-    int tw4;                 // 3D tile width in float4 columns (16 or 8)
+    int shape3;              // 3D tile shape code (16, 8 or kShapeMixed)
+    int nstrip;              // mixed shape: 32 x 32 tiles of the last x column
     int ntz[3], zchunk[3];   // per step mode (kPlain, kBracket, kImage)
     hipStream_t last_stream;   // stream of the latest enqueued work
     bool has_last_stream;
@@ -450,7 +477,13 @@ int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s
             if (ndim == 3) { y = ix[1]; z = ix[2]; } else { z = ix[1]; }
             idx[slot] = L.offset(x, y, z);
             w[slot] = (float)wt;
-            const int tile = ndim == 3 ? (y / tile3_y(g->tw4)) * g->ntx + x / tile3_x(g->tw4) : x / kTileX;
+            int tile;
+            if (ndim != 3)
+                tile = x / kTileX;
+            else if (g->shape3 == kShapeMixed)
+                tile = x < g->ntx * 64 ? (y / 16) * g->ntx + x / 64 : g->ntx * g->nty + y / 32;
+            else
+                tile = (y / tile3_y(g->shape3)) * g->ntx + x / tile3_x(g->shape3);
             if ((float)wt != 0.f) ents.push_back({tile, z, y, x, p, (float)wt});
         }
     }
@@ -480,7 +513,7 @@ int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s
         i = j;
     }
     // plane pointers of every tile: pptr[k] = first corner with key >= k
-    const size_t nptr = (size_t)g->ntx * g->nty * (L.nz + 1);
+    const size_t nptr = (size_t)(g->ntx * g->nty + g->nstrip) * (L.nz + 1);
     std::vector<int> pptr(nptr, 0);
     {
         size_t c = 0;
@@ -543,7 +576,8 @@ StepArgs base_args(const fd_grid *g) {
     a.w0 = (float)(-2.0 * wsum);
     a.ntx = g->ntx;
     a.nty = g->nty;
-    a.tile_w4 = g->tw4;
+    a.shape3 = g->shape3;
+    a.nstrip = g->nstrip;
     a.ntz = g->ntz[kPlain];
     a.zchunk = g->zchunk[kPlain];
     return a;
@@ -672,9 +706,13 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
 
     // launch geometry of each step mode (the gradient modes differ in
     // register use, hence occupancy, hence chunking)
-    g->tw4 = tile_w4(desc, L);
-    g->ntx = desc->ndim == 3 ? (L.nx + tile3_x(g->tw4) - 1) / tile3_x(g->tw4) : (L.nx + kTileX - 1) / kTileX;
-    g->nty = desc->ndim == 3 ? (L.ny + tile3_y(g->tw4) - 1) / tile3_y(g->tw4) : 1;
+    g->shape3 = tile_shape(desc, L);
+    {
+        const TileGrid tg = tile_grid(L, g->shape3);
+        g->ntx = tg.ntx;
+        g->nty = tg.nty;
+        g->nstrip = tg.nstrip;
+    }
     for (int m = 0; m < 3; ++m) {
         if (desc->ndim == 2) {
             g->zchunk[m] = kTile2Z;
@@ -697,8 +735,8 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
                 cus <= 0)
                 cus = 256;
-            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m, g->tw4));
-            const int tiles = std::max(1, g->ntx * g->nty);
+            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m, g->shape3));
+            const int tiles = std::max(1, g->ntx * g->nty + g->nstrip);
             const int kmax = std::min(occ, 3), prefer = g->st == Store::F32 ? 2 : 3;
             int nzc = 1;
             double best = -1.0;
@@ -791,8 +829,10 @@ extern "C" int fd_grid_get_info(const fd_grid *g, fd_grid_info *info) {
     info->critical_dt = g->dt_crit;
     info->damp_max = g->sigma_max;
     info->field_bytes = g->wp.field_bytes;
-    info->tile[0] = g->d.ndim == 3 ? tile3_x(g->tw4) : kTileX;
-    info->tile[1] = g->d.ndim == 3 ? tile3_y(g->tw4) : kTile2Z;
+    const int tw4 = g->shape3 == kShapeMixed ? 16 : g->shape3;
+    info->tile[0] = g->d.ndim == 3 ? tile3_x(tw4) : kTileX;
+    info->tile[1] = g->d.ndim == 3 ? tile3_y(tw4) : kTile2Z;
+    info->tile_strip = g->nstrip > 0 ? g->L.nx - 64 * g->ntx : 0;
     info->zchunk = g->zchunk[kPlain];
     return FD_OK;
 }

@@ -17,7 +17,11 @@ constexpr int kBlock = 256;       // threads per workgroup
 constexpr int kMaxChunk = 512;    // z planes per 3D workgroup at most
 
 // 3D step tiles have tw4 float4 columns per row: 16 (64 x 16 points) or 8
-// (32 x 32 points); either way one point quad per lane of a workgroup.
+// (32 x 32 points); either way one point quad per lane of a workgroup.  A
+// grid's tile shape code is 16 or 8 (every tile so), or kShapeMixed: 64 x 16
+// tiles over the whole 64-point x columns and 32 x 32 tiles for the last
+// column, when it is at most 32 points wide.
+constexpr int kShapeMixed = 0;
 inline int tile3_x(int tw4) { return 4 * tw4; }
 inline int tile3_y(int tw4) { return kBlock / tw4; }
 
@@ -102,8 +106,9 @@ struct StepArgs {
     float wx[kMaxR + 1];    // c_j / h_x^2
     float wy[kMaxR + 1];
     float wz[kMaxR + 1];
-    int ntx, nty, ntz;      // tiles per axis (ntz counts z chunks in 3D)
-    int tile_w4;            // 3D tile width in float4 columns (16 or 8)
+    int ntx, nty, ntz;      // tiles per axis (3D mixed shape: of the 64 x 16 tiles; ntz counts z chunks)
+    int shape3;             // 3D tile shape code: 16, 8 or kShapeMixed
+    int nstrip;             // mixed shape: 32 x 32 tiles of the last x column (else 0)
     int zchunk;             // planes per 3D workgroup
     int nsamp_blocks;       // trailing workgroups that sample instead of stepping
     Inject inj;
@@ -114,7 +119,7 @@ struct StepArgs {
 enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
 
 // Resident workgroups per CU of a step kernel (0 if unknown).
-int step_blocks_per_cu(int ndim, int r, Store st, int mode, int tw4);
+int step_blocks_per_cu(int ndim, int r, Store st, int mode, int shape3);
 
 // Launchers (fd_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s);

@@ -252,33 +252,37 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
-// TW float4 columns per tile row: 16 (64 x 16 tiles) or 8 (32 x 32 tiles).
+// Shared memory of a 3D step workgroup with tiles of TW float4 columns,
+// carved from one buffer (offsets in float4) so that a launch that mixes
+// tile shapes reserves only the larger layout.
+template <int R, int TW>
+struct Smem3 {
+    static constexpr int TY = kBlock / TW, HX4 = (R + 3) / 4, W4 = TW + 2 * HX4, LH = TY + 2 * R;
+    static constexpr int NH = 2 * R * TW + 2 * TY * HX4;     // halo items of a plane
+    static constexpr int kLds = 0;                           // [2][LH * W4] staged planes
+    static constexpr int kRing = kLds + 2 * LH * W4;         // [(R + 1) * NH] halo ring
+    static constexpr int kSrc = kRing + (R + 1) * NH;        // [kBlock] source terms of a plane
+    static constexpr int kDz = kSrc + kBlock;                // float [kMaxChunk] z damping
+    static constexpr int kPp = kDz + kMaxChunk / 4;          // int [kMaxChunk + 1] plane pointers
+    static constexpr int kSize = kPp + (kMaxChunk + 1 + 3) / 4;
+};
+
+// One workgroup's step: the xy tile at (x0, y0) of TW float4 columns per
+// row (16: 64 x 16 points, 8: 32 x 32) and z chunk bz; tid is the tile's
+// row in the source plane-pointer table.
 template <int R, Store S, int MODE, int TW>
-__global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
+__device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int x0, int y0, int bz, int tid) {
     using E = Elem<S>;
     using T = typename E::T;
+    using SM = Smem3<R, TW>;
     constexpr int TX = 4 * TW;                // x points per tile
     constexpr int TY = kBlock / TW;           // y rows per tile
     constexpr int HX4 = (R + 3) / 4;          // float4 halo columns per side
     constexpr int W4 = TW + 2 * HX4;          // float4 per LDS row
     constexpr int LH = TY + 2 * R;            // LDS rows
-    __shared__ float4 lds[2][LH * W4];
+    float4 (*lds)[LH * W4] = reinterpret_cast<float4 (*)[LH * W4]>(smem + SM::kLds);
 
     const Layout L = a.L;
-    // Tile workgroups come first in dispatch order (renumbered per XCD); the
-    // sampling workgroups trail them and take free slots, so they never
-    // displace a tile into a second round.
-    const int ntile = (int)gridDim.x - a.nsamp_blocks;
-    if ((int)blockIdx.x >= ntile) {
-        sample_block<S>(a.smp, a.u, (int)blockIdx.x - ntile);
-        return;
-    }
-    int t = xcd_remap((int)blockIdx.x, ntile);
-    const int bx = t % a.ntx;
-    t /= a.ntx;
-    const int by = t % a.nty;
-    const int bz = t / a.nty;
-    const int x0 = bx * TX, y0 = by * TY;
     const int z0 = bz * a.zchunk;
     const int z1 = min(z0 + a.zchunk, L.nz);
     // Odd chunks march downwards: two adjacent chunks then read the warm-up
@@ -293,16 +297,17 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     // Per-plane tables of this chunk (damping along z, source CSR pointers)
     // are staged in LDS so that the plane loop issues no uniform global load:
     // a vector-memory wait for one would also drain the prefetched planes.
-    __shared__ float s_dz[kMaxChunk];
-    __shared__ int s_pp[kMaxChunk + 1];
-    const int *tile_pp = a.inj.plane_ptr + (long long)(by * a.ntx + bx) * (L.nz + 1);
+    float *s_dz = reinterpret_cast<float *>(smem + SM::kDz);
+    int *s_pp = reinterpret_cast<int *>(smem + SM::kPp);
+    const int *tile_pp = a.inj.plane_ptr + (long long)tid * (L.nz + 1);
     for (int i = lane; i <= z1 - z0; i += kBlock) {
         if (i < z1 - z0) s_dz[i] = a.damp[L.nx + L.ny + z0 + i];
         s_pp[i] = a.inj.vals ? tile_pp[z0 + i] : 0;
     }
     // Source terms of the current plane, scattered by the workgroup (one
     // float4 per lane; a lane clears its cells after reading them).
-    __shared__ float4 s_src4[TY * TX / 4];
+    static_assert(TY * TX / 4 == kBlock, "one float4 of source terms per lane");
+    float4 *s_src4 = smem + SM::kSrc;
     s_src4[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     const int tx = lane % TW, ty = lane / TW;
     const int x = x0 + 4 * tx, y = y0 + ty;
@@ -380,7 +385,8 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     // z as its queue front R planes before this tile stages plane z; loading
     // the halo at that same time lets the neighbour's fetch serve it from L2.
     constexpr int kRing = R + 1;
-    __shared__ float4 ring[kRing * NH];
+    static_assert(NH == SM::NH, "halo layout");
+    float4 *ring = smem + SM::kRing;
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
@@ -538,6 +544,40 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
         constexpr int i = decltype(I)::value;
         if (st + i < len) body(I, st + i, set(I), set(std::integral_constant<int, i + 2>{}));
     });
+}
+
+// The 3D step.  SHAPE 16 or 8: every tile has that many float4 columns.
+// SHAPE 0: 64 x 16 tiles over the ntx whole 64-point columns and, beside
+// them, nstrip 32 x 32 tiles for the last, narrower x column (at most 32
+// points), which a 64-point tile would fill to half or less.  Tiles are
+// numbered x fastest, then y, then the strip, then z chunk.
+template <int R, Store S, int MODE, int SHAPE>
+__global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
+    constexpr int kSmem = SHAPE == 16 ? Smem3<R, 16>::kSize
+                          : SHAPE == 8 ? Smem3<R, 8>::kSize
+                                       : (Smem3<R, 16>::kSize > Smem3<R, 8>::kSize ? Smem3<R, 16>::kSize
+                                                                                 : Smem3<R, 8>::kSize);
+    __shared__ float4 smem[kSmem];
+    // Tile workgroups come first in dispatch order (renumbered per XCD); the
+    // sampling workgroups trail them and take free slots, so they never
+    // displace a tile into a second round.
+    const int ntile = (int)gridDim.x - a.nsamp_blocks;
+    if ((int)blockIdx.x >= ntile) {
+        sample_block<S>(a.smp, a.u, (int)blockIdx.x - ntile);
+        return;
+    }
+    const int t = xcd_remap((int)blockIdx.x, ntile);
+    const int nmain = a.ntx * a.nty;
+    const int tiles = nmain + a.nstrip;
+    const int u = t % tiles, bz = t / tiles;
+    if constexpr (SHAPE == 0) {
+        if (u < nmain)
+            step3d_tile<R, S, MODE, 16>(a, smem, (u % a.ntx) * 64, (u / a.ntx) * 16, bz, u);
+        else
+            step3d_tile<R, S, MODE, 8>(a, smem, a.ntx * 64, (u - nmain) * 32, bz, u);
+    } else {
+        step3d_tile<R, S, MODE, SHAPE>(a, smem, (u % a.ntx) * 4 * SHAPE, (u / a.ntx) * (kBlock / SHAPE), bz, u);
+    }
 }
 
 // ------------------------------------------------------------------ 2D step
@@ -995,10 +1035,12 @@ using StepFn = void (*)(const StepArgs);
 
 template <Store S, int MODE, int... Rs>
 struct Table {
-    static StepFn get3(int r, int tw4) {
+    static StepFn get3(int r, int shape) {
         StepFn f = nullptr;
-        if (tw4 == 16) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 16>, 0) : 0), ...);
-        if (tw4 == 8) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 8>, 0) : 0), ...);
+        if (shape == 16) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 16>, 0) : 0), ...);
+        if (shape == 8) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 8>, 0) : 0), ...);
+        // (radii 7 and 8 always run 32 x 32 tiles: no mixed kernel)
+        if (shape == 0) ((r == Rs ? (f = k_step3d<Rs, S, MODE, (Rs <= 6 ? 0 : 8)>, 0) : 0), ...);
         return f;
     }
     static StepFn get2(int r) {
@@ -1036,9 +1078,9 @@ inline int grid_for(long long n) {
 }  // namespace
 
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s) {
-    StepFn f = pick_step(a.L.ndim, a.L.r, st, mode, a.tile_w4);
+    StepFn f = pick_step(a.L.ndim, a.L.r, st, mode, a.shape3);
     if (!f) return hipErrorInvalidValue;
-    const int tiles = a.ntx * a.nty * a.ntz;
+    const int tiles = (a.ntx * a.nty + (a.L.ndim == 3 ? a.nstrip : 0)) * a.ntz;
     const int blocks = tiles + a.nsamp_blocks;
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(f, dim3(blocks), dim3(kBlock), 0, s, a);

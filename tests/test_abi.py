@@ -61,14 +61,14 @@ def test_workspace_bytes_grow_with_grid(lib):
     rc3, b3 = _bytes(lib, _desc(shape=(64, 48, 32), storage=_lib.FD_STORE_BF16))
     assert rc3 == 0 and b3 < b1
     # either 3D tile shape is a valid description (their source tables differ)
-    for tx in (32, 64):
+    for tx in (32, 64, 96):
         rc4, b4 = _bytes(lib, _desc(shape=(64, 48, 32), tile_x=tx))
         assert rc4 == 0 and b4 > 0
 
 
 @pytest.mark.parametrize("bad", [
     dict(ndim=4), dict(so=3), dict(so=18), dict(so=0), dict(nbl=-1), dict(shape=(1, 8, 8)),
-    dict(storage=7), dict(tile_x=48), dict(tile_x=-32),
+    dict(storage=7), dict(tile_x=48), dict(tile_x=-32), dict(tile_x=128),
 ])
 def test_invalid_descriptors_rejected(lib, bad):
     rc, _ = _bytes(lib, _desc(**bad))

@@ -15,11 +15,12 @@ from gpu_common import case, gpu_forward, gpu_grid, need_gpu, oracle_forward, re
 pytestmark = pytest.mark.gpu
 
 
-def _both(c, **kw):
+def _shapes(c, shapes=(64, 32, 96), **kw):
     out = []
-    for tx in (64, 32):
+    for tx in shapes:
         g = gpu_grid(c, tile_x=tx, **kw)
-        assert g.tile == ((64, 16) if tx == 64 else (32, 32))
+        assert g.tile == ((32, 32) if tx == 32 else (64, 16))
+        assert (g.tile_strip > 0) == (tx == 96)
         _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
         out.append((rec, state))
         g.close()
@@ -29,15 +30,19 @@ def _both(c, **kw):
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("so", [4, 8, 16])
 def test_forward_bitwise_across_tile_shapes(storage, so):
-    """90 x 70 x 33 + 6: ragged last tiles in x and y under both shapes,
-    4 sources, 13 receivers, 50 steps."""
+    """80 x 70 x 33 + 6 (92 x 82 x 45 padded): ragged last tiles in x and y
+    under every shape, the mixed one with a 28-point strip of 32 x 32
+    tiles; 4 sources, 13 receivers, 50 steps."""
     need_gpu()
-    c = case((90, 70, 33), so, 6, 50, seed=40 + so, nsrc=4, nrec=13)
-    (r1, s1), (r2, s2) = _both(c, storage=storage)
-    print("tiles %s so=%d: traces equal %d, field equal %d" % (storage, so, int(torch.equal(r1, r2)),
-                                                               int(torch.equal(s1[0], s2[0]))), flush=True)
-    assert torch.equal(r1, r2)
-    assert torch.equal(s1[0], s2[0]) and torch.equal(s1[1], s2[1])
+    c = case((80, 70, 33), so, 6, 50, seed=40 + so, nsrc=4, nrec=13)
+    shapes = (64, 32, 96) if so < 14 else (64, 32)
+    res = _shapes(c, shapes, storage=storage)
+    (r1, s1) = res[0]
+    for tx, (r2, s2) in zip(shapes[1:], res[1:]):
+        print("tiles %s so=%d, %d vs 64: traces equal %d, field equal %d" % (
+            storage, so, tx, int(torch.equal(r1, r2)), int(torch.equal(s1[0], s2[0]))), flush=True)
+        assert torch.equal(r1, r2)
+        assert torch.equal(s1[0], s2[0]) and torch.equal(s1[1], s2[1])
 
 
 def test_narrow_tiles_against_oracle_many_sources():
@@ -65,34 +70,39 @@ def test_adjoint_and_gradient_bitwise_across_tile_shapes():
     rng = np.random.default_rng(4)
     obs = torch.from_numpy(rng.standard_normal((c["nt"], len(c["rec"]))).astype(np.float32) * 1e-3).to(dev)
     outs = []
-    for tx in (64, 32):
+    for tx in (64, 32, 96):
         g = gpu_grid(c, tile_x=tx)
+        assert (g.tile_strip > 0) == (tx == 96)
         adj = g.adjoint(c["src"], c["rec"], obs, c["dt"])
         grads = [g.gradient(c["src"], wav, c["rec"], obs, c["dt"], checkpoint_every=K) for K in (9, c["nt"])]
         torch.cuda.synchronize()
         outs.append((adj, grads))
         g.close()
-    (a1, g1), (a2, g2) = outs
-    assert torch.equal(a1, a2)
-    for x, y in zip(g1, g2):
-        assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1]) and torch.equal(x[2], y[2])
+    (a1, g1) = outs[0]
+    for (a2, g2) in outs[1:]:
+        assert torch.equal(a1, a2)
+        for x, y in zip(g1, g2):
+            assert torch.equal(x[0], y[0]) and torch.equal(x[1], y[1]) and torch.equal(x[2], y[2])
     print("adjoint and gradients bitwise equal across tile shapes", flush=True)
 
 
-@pytest.mark.parametrize("shape,so,want", [
-    ((200, 200, 40), 8, (64, 16)),     # so <= 8: always 64 x 16
-    ((200, 200, 40), 12, (32, 32)),    # so 10, 12, padded x 280 = 4.375 x 64: ragged rows
-    ((240, 200, 40), 12, (64, 16)),    # padded x 320: whole 64-point rows
-    ((256, 256, 40), 12, (64, 16)),    # padded 336: 87.5 % vs 91 % of lanes used, too close
-    ((240, 200, 40), 16, (32, 32)),    # so >= 14: always 32 x 32
-    ((31, 20), 16, (64, 64)),          # 2D: 64 x-points by 64 z-rows
+@pytest.mark.parametrize("shape,so,storage,want,strip", [
+    ((200, 200, 40), 8, "f32", (64, 16), 24),    # padded x 280 = 4 x 64 + a 24-point strip of 32 x 32
+    ((240, 200, 40), 8, "f32", (64, 16), 0),     # padded x 320: whole 64-point columns only
+    ((230, 200, 40), 8, "f32", (64, 16), 0),     # padded x 310: a 54-point last column stays 64 x 16
+    ((200, 200, 40), 8, "bf16", (64, 16), 0),    # 16-bit: no strip (half-line rows)
+    ((200, 200, 40), 12, "f32", (64, 16), 24),   # so 12 on 280: the strip beats 32 x 32 tiles
+    ((200, 200, 40), 12, "f16", (32, 32), 0),    # 16-bit so 12 on 280: 32 x 32 uses 9 % more lanes
+    ((240, 200, 40), 12, "f16", (64, 16), 0),    # padded x 320: whole 64-point rows
+    ((240, 200, 40), 16, "f32", (32, 32), 0),    # so >= 14: always 32 x 32
+    ((31, 20), 16, "f32", (64, 64), 0),          # 2D: 64 x-points by 64 z-rows
 ])
-def test_automatic_tile_choice(shape, so, want):
+def test_automatic_tile_choice(shape, so, storage, want, strip):
     need_gpu()
     dev = torch.device("cuda:0")
     from paper_1906_10811_amd import Grid
     v = torch.full(tuple(reversed(shape)), 2000.0, device=dev)
-    g = Grid(shape, (10.0,) * len(shape), v, space_order=so, nbl=40)
-    print("padded", g.padded, "so", so, "tile", g.tile, "zchunk", g.zchunk, flush=True)
-    assert g.tile == want
+    g = Grid(shape, (10.0,) * len(shape), v, space_order=so, nbl=40, storage=storage)
+    print("padded", g.padded, "so", so, "tile", g.tile, "strip", g.tile_strip, "zchunk", g.zchunk, flush=True)
+    assert g.tile == want and g.tile_strip == strip
     g.close()
