@@ -47,7 +47,9 @@ struct Layout {
 
 // Per-tile, per-plane CSR of the grid points that receive a point-source
 // term in a step.  The tiles are those of the step kernels (64 x 16 or
-// 32 x 32 in xy for 3D, 64 in x for 2D), numbered tile = ty * ntx + tx.  Corner k lies at
+// 32 x 32 in xy for 3D, 64 in x for 2D), numbered tile = ty * ntx + tx; in
+// the mixed 3D shape the 32 x 32 tiles of the last x column follow, as
+// ntx * nty + y / 32.  Corner k lies at
 // (x, y) of plane z inside tile t with
 //   plane_ptr[t * (nz + 1) + z] <= k < plane_ptr[t * (nz + 1) + z + 1];
 // each grid point appears at most once, and its value is
