@@ -106,3 +106,29 @@ def test_automatic_tile_choice(shape, so, storage, want, strip):
     print("padded", g.padded, "so", so, "tile", g.tile, "strip", g.tile_strip, "zchunk", g.zchunk, flush=True)
     assert g.tile == want and g.tile_strip == strip
     g.close()
+
+
+@pytest.mark.parametrize("sinc", [0, 4])
+def test_sources_on_the_strip_seam(sinc):
+    """Mixed shape: sources on both sides of the seam between the 64 x 16
+    tiles and the 32 x 32 strip (padded x 63, 64, 65 and inside the strip),
+    windowed-sinc nodes that straddle it, receivers likewise; bitwise equal
+    to 64 x 16 tiles alone and within the gate of the oracle."""
+    need_gpu()
+    c = case((76, 40, 30), 8, 3, 50, seed=31, nsrc=1, nrec=1)   # padded x 82: seam at 64, strip of 18
+    h, o = c["spacing"], c["origin"]
+    xs = [60.5, 63.0, 63.7, 64.0, 64.4, 70.2, 77.6]            # padded x (physical x + 3)
+    c["src"] = [(o[0] + (x - 3) * h[0], o[1] + (9.3 + 3 * k) * h[1], o[2] + (11.6 + k) * h[2])
+                for k, x in enumerate(xs)]
+    c["rec"] = np.array([[o[0] + (x - 3 + 0.37) * h[0], o[1] + 20.5 * h[1], o[2] + 6.2 * h[2]] for x in xs])
+    rng = np.random.default_rng(2)
+    c["wav"] = (rng.standard_normal((c["nt"], len(xs))) * np.hanning(c["nt"])[:, None]).astype(np.float32)
+    c["sinc"] = sinc
+    want, u_nt, _, _ = oracle_forward(c)
+    (r1, s1), (r2, s2) = _shapes(c, (64, 96))
+    e_rec = rel_l2(r2.cpu().numpy(), want)
+    e_u = rel_l2(s2[0].cpu().numpy(), u_nt)
+    print("seam sinc=%d: traces %.3e field %.3e, bitwise %d" % (sinc, e_rec, e_u, int(torch.equal(r1, r2))),
+          flush=True)
+    assert torch.equal(r1, r2) and torch.equal(s1[0], s2[0])
+    assert e_rec <= 1e-5 and e_u <= 1e-5
