@@ -108,10 +108,12 @@ def _smooth_state(shape_np, seed):
     return f
 
 
-@pytest.mark.parametrize("name,shape", [("layered3d_256", None), ("grf3d_512", (512, 512, 512))])
+@pytest.mark.parametrize("name,shape", [("layered3d_256", None), ("grf3d_512", (512, 512, 512)),
+                                        ("gradient3d_200", None)])
 def test_full_size_in_bench_launch_shape(name, shape):
-    """The benchmark's grids (336^3 and 592^3 padded, so 8) in their
-    automatic launch shape: a few steps from a smooth random state with a
+    """The benchmark's grids (336^3, 592^3 and 280^3 padded, so 8) in their
+    automatic launch shape (64 x 16 tiles with a last column of 32 x 32: 16,
+    16 and 24 points wide): a few steps from a smooth random state with a
     source firing at its peak, every point of the final field and every
     trace sample against the oracle run on the whole grid."""
     need_gpu()
@@ -142,6 +144,39 @@ def test_full_size_in_bench_launch_shape(name, shape):
     er = rel_l2(got_rec, want_rec)
     print("full size %s (%s padded), %d steps: field %.3e, traces %.3e" % (name, g0.padded, nt, eu, er))
     assert eu <= 1e-5 and er <= 1e-5
+
+
+def test_full_size_gradient_schedules_agree():
+    """gradient3d_200 as the benchmark runs it (280^3 padded, so 8, 800
+    steps, mixed tiles): checkpoints every 50 steps, every bracket resident,
+    and the binomial schedule with 16 snapshot slots give bitwise the same
+    misfit, gradient and traces."""
+    need_gpu()
+    from paper_1906_10811_amd import Grid
+    w = synth.workload("gradient3d_200")
+    v_true = synth.velocity(w)
+    v0 = synth.smooth_model(v_true, w["spacing"], 100.0)
+    dev = torch.device("cuda:0")
+    wav = torch.from_numpy(synth.wavelets(w)).to(dev)
+    gt = Grid(w["shape"], w["spacing"], torch.from_numpy(v_true).to(dev), space_order=8, nbl=w["nbl"])
+    d_obs = gt.forward(w["src"], wav, w["rec"], w["dt"])
+    torch.cuda.synchronize()
+    gt.close()
+    g = Grid(w["shape"], w["spacing"], torch.from_numpy(v0).to(dev), space_order=8, nbl=w["nbl"])
+    assert g.tile_strip == 24
+    m1, g1, r1, _ = g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], checkpoint_every=w["checkpoint_every"])
+    torch.cuda.synchronize()
+    m2, g2, r2, _ = g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], checkpoint_every=w["nt"])
+    torch.cuda.synchronize()
+    same_resident = bool(torch.equal(m1, m2) and torch.equal(g1, g2) and torch.equal(r1, r2))
+    del g2, r2
+    m3, g3, r3, _ = g.gradient(w["src"], wav, w["rec"], d_obs, w["dt"], binomial_slots=16)
+    torch.cuda.synchronize()
+    same_binomial = bool(torch.equal(m1, m3) and torch.equal(g1, g3) and torch.equal(r1, r3))
+    print("full-size gradient: misfit %.6e, |g| %.6e, resident bitwise %d, binomial bitwise %d" % (
+        m1.item(), g1.norm().item(), int(same_resident), int(same_binomial)), flush=True)
+    assert math.isfinite(m1.item()) and m1.item() > 0 and g1.norm().item() > 0
+    assert same_resident and same_binomial
 
 
 def test_full_length_properties_layered3d_256():
