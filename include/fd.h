@@ -101,8 +101,9 @@ typedef struct fd_grid_desc {
     double sinc_beta;      /* Kaiser shape b; <= 0 selects pi * sinc_radius / 2 */
     int tile_x;            /* 3D workgroup tiles: 64 (64 x 16 xy tiles), 32 (32 x 32), 96
                               (64 x 16, and 32 x 32 for a last x column of at most 32
-                              points; 64 x 16 alone when there is none), 0 selects
-                              automatically; ignored in 2D */
+                              points; 64 x 16 alone when there is none; space orders 14
+                              and 16 run 32 x 32 instead), 0 selects automatically; any
+                              other value is FD_ERR_ARG; ignored in 2D */
 } fd_grid_desc;
 
 /* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
