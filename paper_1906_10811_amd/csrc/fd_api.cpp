@@ -987,7 +987,10 @@ GradPlan grad_plan(const fd_grid *g, int nt, int nrec, int K, int flags) {
     const size_t fb = g->wp.field_bytes;
     size_t o = 0;
     p.ckpt = o; o += fb * 2 * (size_t)p.ncp;
-    p.rot = o; o += fb * 2;
+    // two working fields for the resident and binomial schedules (the fixed
+    // interval recomputes each segment in its checkpoint's fields)
+    p.rot = o;
+    if (p.binomial || K >= nt) o += fb * 2;
     p.br = o; o += fb * (size_t)p.nbr;
     p.grad = o; o = align_up(o + sizeof(double) * (size_t)g->L.elems, 256);
     p.gpart = o; o = align_up(o + sizeof(float) * (size_t)g->L.elems, 256);
@@ -1037,7 +1040,7 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     const size_t fb = g->wp.field_bytes;
     std::vector<void *> ck((size_t)2 * gp.ncp);
     for (int i = 0; i < 2 * gp.ncp; ++i) ck[i] = ws + gp.ckpt + fb * (size_t)i;
-    void *rotA = ws + gp.rot, *rotB = ws + gp.rot + fb;
+    void *rotA = ws + gp.rot, *rotB = ws + gp.rot + fb;   // (not allocated for the fixed interval, which does not use them)
     std::vector<float *> br(gp.nbr);
     for (int i = 0; i < gp.nbr; ++i) br[i] = (float *)(ws + gp.br + fb * (size_t)i);
     double *gacc = (double *)(ws + gp.grad);
@@ -1088,7 +1091,7 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
         a.zchunk = g->zchunk[kImage];
         HIPCHK(launch_step(a, g->st, kImage, s));
         std::swap(LA, LB);
-        if (++adj_done % kFoldEvery == 0) HIPCHK(launch_fold_f64(gacc, gpart, L.elems, s));
+        if (++adj_done % kFoldEvery == 0) HIPCHK(launch_fold_f64(L, gacc, gpart, s));
         return FD_OK;
     };
     HIPCHK(launch_zero_f64(gacc, L.elems, s));
@@ -1144,9 +1147,8 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
             const int c = seg * K;
             const int e = std::min(c + K, nt);
             if (c != clast) {
-                HIPCHK(hipMemcpyAsync(rotA, ck[2 * seg], fb, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(rotB, ck[2 * seg + 1], fb, hipMemcpyDeviceToDevice, s));
-                void *A = rotA, *B = rotB;   // u^n, u^{n-1}
+                // each checkpoint serves one recompute: step in its own fields
+                void *A = ck[2 * seg], *B = ck[2 * seg + 1];   // u^n, u^{n-1}
                 for (int n = c; n < e; ++n) {
                     if ((rc = bracket_step(n, A, B, B, br[n - c], nullptr))) return rc;
                     std::swap(A, B);
@@ -1247,7 +1249,7 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
             }
         }
     }
-    if (adj_done % kFoldEvery) HIPCHK(launch_fold_f64(gacc, gpart, L.elems, s));
+    if (adj_done % kFoldEvery) HIPCHK(launch_fold_f64(L, gacc, gpart, s));
     HIPCHK(launch_field_to_dense_f64(L, gacc, grad_m, s));
     if (src_adj) {
         Sample sm = make_sample(g, 0, sh->nsrc, src_adj, adj_smp);

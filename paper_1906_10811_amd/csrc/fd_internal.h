@@ -146,8 +146,9 @@ hipError_t launch_diffuse2d_tb(const Layout &L, const float *u, float *out, floa
 hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
                          float *resid, double *partials, int npart, double *out, hipStream_t s);
 hipError_t launch_zero_f64(double *p, long long n, hipStream_t s);
-// acc[i] += part[i]; part[i] = 0 for i < n (n a multiple of 4, 16-B aligned)
-hipError_t launch_fold_f64(double *acc, float *part, long long n, hipStream_t s);
+// acc += part; part = 0 over the grid rows of two pitched fields of layout L
+// (float64 and float32); halo and pad cells are not touched.
+hipError_t launch_fold_f64(const Layout &L, double *acc, float *part, hipStream_t s);
 hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, double *dense, hipStream_t s);
 
 }  // namespace fd

@@ -1136,11 +1136,19 @@ hipError_t launch_zero_field(const Layout &L, void *f, Store st, hipStream_t s) 
     return hipGetLastError();
 }
 
-__global__ void k_fold_f64(double *acc, float *part, long long n4) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4;
+// acc += part, part = 0, over the grid rows of the two pitched fields (x in
+// [0, round4(nx)): the cells past nx are zero in both, so they stay zero);
+// the zero halo and pad are left alone.
+__global__ void k_fold_f64(double *acc, float *part, const Layout L) {
+    const int g4 = (L.nx + 3) / 4;   // float4 groups per row
+    const long long n = (long long)g4 * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const float4 p = reinterpret_cast<const float4 *>(part)[i];
-        double2 *a = reinterpret_cast<double2 *>(acc) + 2 * i;
+        const long long row = i / g4;
+        const int gx = (int)(i - row * g4);
+        const long long off = L.offset(4 * gx, (int)(row % L.ny), (int)(row / L.ny));   // a multiple of 4
+        const float4 p = *reinterpret_cast<const float4 *>(part + off);
+        double2 *a = reinterpret_cast<double2 *>(acc + off);
         double2 a0 = a[0], a1 = a[1];
         a0.x += p.x;
         a0.y += p.y;
@@ -1148,13 +1156,13 @@ __global__ void k_fold_f64(double *acc, float *part, long long n4) {
         a1.y += p.w;
         a[0] = a0;
         a[1] = a1;
-        reinterpret_cast<float4 *>(part)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        *reinterpret_cast<float4 *>(part + off) = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
-hipError_t launch_fold_f64(double *acc, float *part, long long n, hipStream_t s) {
-    if (n % 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fold_f64, dim3(grid_for(n / 4)), dim3(kBlock), 0, s, acc, part, n / 4);
+hipError_t launch_fold_f64(const Layout &L, double *acc, float *part, hipStream_t s) {
+    const long long n = (long long)((L.nx + 3) / 4) * L.ny * L.nz;
+    hipLaunchKernelGGL(k_fold_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, acc, part, L);
     return hipGetLastError();
 }
 
