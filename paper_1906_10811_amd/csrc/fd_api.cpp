@@ -165,6 +165,7 @@ struct WsPlan {
 };
 
 constexpr int kNPart = 512;   // misfit partial sums
+constexpr size_t kCachedField = size_t(128) << 20;   // largest 16-bit field stored with ordinary stores
 constexpr int kFoldEvery = 32;   // adjoint steps per float32 partial gradient sum
 
 size_t side_bytes(int cap, int nc, size_t nptr, size_t off[6], size_t base) {
@@ -578,6 +579,14 @@ StepArgs base_args(const fd_grid *g) {
     a.nty = g->nty;
     a.shape3 = g->shape3;
     a.nstrip = g->nstrip;
+    // The new level is the next step's centre field.  A 16-bit field of up to
+    // kCachedField bytes is stored with ordinary stores, so that it can still
+    // sit in the memory-side cache (256 MB) when the next step reads it:
+    // measured +4 % (336^3, 106 MB) and +3 % (280^3, 64 MB) in bfloat16, but
+    // -12 % at 592^3 (507 MB); in float32 ordinary stores lost 20 % at 336^3
+    // and 7 % at 280^3 (the written lines crowd out of L2 the neighbour rows
+    // that the halo loads expect there).
+    a.out_cached = (g->st != Store::F32 && g->wp.field_bytes <= kCachedField) ? 1 : 0;
     a.ntz = g->ntz[kPlain];
     a.zchunk = g->zchunk[kPlain];
     return a;

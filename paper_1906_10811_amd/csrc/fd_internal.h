@@ -111,6 +111,7 @@ struct StepArgs {
     int ntx, nty, ntz;      // tiles per axis (3D mixed shape: of the 64 x 16 tiles; ntz counts z chunks)
     int shape3;             // 3D tile shape code: 16, 8 or kShapeMixed
     int nstrip;             // mixed shape: 32 x 32 tiles of the last x column (else 0)
+    int out_cached;         // 3D: store u^{n+1} with an ordinary store, not a non-temporal one
     int zchunk;             // planes per 3D workgroup
     int nsamp_blocks;       // trailing workgroups that sample instead of stepping
     Inject inj;

@@ -66,6 +66,7 @@ template <> struct Elem<Store::F32> {
     __device__ static Raw ld4ntraw(const T *p) { return ld4nt(p); }
     __device__ static float4 cvt(const Raw &r) { return r; }
     __device__ static void st4nt(T *p, float4 v) { st4nt_f32(p, v); }
+    __device__ static void st4(T *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
     __device__ static float ld(const T *p) { return *p; }
     __device__ static void st(T *p, float v) { *p = v; }
 };
@@ -97,6 +98,7 @@ template <typename Cvt> struct Elem16 {
     __device__ static Raw ld4ntraw(const T *p) { return ld2nt_u32(p); }
     __device__ static float4 cvt(const Raw &r) { return unpack(r); }
     __device__ static void st4nt(T *p, float4 v) { st2nt_u32(p, pack(v)); }
+    __device__ static void st4(T *p, float4 v) { *reinterpret_cast<uint2 *>(p) = pack(v); }
     __device__ static float ld(const T *p) { return Cvt::to_f(*p); }
     __device__ static void st(T *p, float v) { *p = Cvt::from_f(v); }
 };
@@ -499,7 +501,11 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
             asm volatile("" ::"v"(r4.x), "v"(r4.y), "v"(r4.z), "v"(r4.w));
             const int nvalid = L.nx - x;
             if (nvalid >= 4) {
-                E::st4nt(O + off, r4);
+                // (float32 fields always stream the new level past the caches)
+                if (S != Store::F32 && a.out_cached)
+                    E::st4(O + off, r4);
+                else
+                    E::st4nt(O + off, r4);
             } else {
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
