@@ -493,12 +493,20 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
                 un[i] = update_point(comp(QQ(R), i), comp(mvf, i), comp(cur.pv, i), lap[i], src[i],
                                      sxy[i] + sz);
             const long long off = base + (long long)z * plane;
-            const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
+            float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
             // All four results are computed here, before the ragged-edge
             // branch: otherwise the compiler sinks the fourth point's
             // Laplacian into the full-width store path and re-reads its LDS
-            // neighbours one at a time there, serialising LDS latency.
-            asm volatile("" ::"v"(r4.x), "v"(r4.y), "v"(r4.z), "v"(r4.w));
+            // neighbours one at a time there, serialising LDS latency.  For
+            // 16-bit storage the values also pass through as opaque float32
+            // values, so that each is rounded to float32 and then to 16 bits
+            // as written; otherwise the compiler may fuse a point's last
+            // multiply into its conversion (one rounding instead of two),
+            // point by point as code generation decides.
+            if constexpr (S == Store::F32)
+                asm volatile("" ::"v"(r4.x), "v"(r4.y), "v"(r4.z), "v"(r4.w));
+            else
+                asm volatile("" : "+v"(r4.x), "+v"(r4.y), "+v"(r4.z), "+v"(r4.w));
             const int nvalid = L.nx - x;
             if (nvalid >= 4) {
                 // (float32 fields always stream the new level past the caches)
@@ -507,9 +515,10 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
                 else
                     E::st4nt(O + off, r4);
             } else {
+                const float rv[3] = {r4.x, r4.y, r4.z};
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
-                    if (i < nvalid) E::st(O + off + i, un[i]);
+                    if (i < nvalid) E::st(O + off + i, rv[i]);
             }
             if constexpr (MODE == kBracket) {
                 float sv[4];
