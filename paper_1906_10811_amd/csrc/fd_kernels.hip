@@ -684,6 +684,8 @@ __global__ __launch_bounds__(kBlock) void k_step2d(const StepArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             un[i] = update_point(comp(cc, i), comp(mc, i), comp(pc, i), lap[i], src[i], sx[i] + sz);
+        if constexpr (S != Store::F32)   // round to float32, then to 16 bits (no fused conversion)
+            asm volatile("" : "+v"(un[0]), "+v"(un[1]), "+v"(un[2]), "+v"(un[3]));
         if (nvalid >= 4) {
             E::st4nt(O + off, make_float4(un[0], un[1], un[2], un[3]));
         } else {
