@@ -445,8 +445,8 @@ def main():
                     help="comma list of adjoint,gradient,precision,grf512,serving,diffusion,sinc or all/none")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: every box in this setup has a single MI355X, and the "
-              "multi-GPU sharding of the stepper is a design, not an implementation",
+        print("bench.py measures one GPU only (--gpus 1): the multi-GPU sharding of the stepper "
+              "(shots across GPUs, z slabs for a shot too large for one GPU) is not implemented",
               file=sys.stderr)
         sys.exit(2)
     import torch
