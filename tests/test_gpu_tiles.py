@@ -1,11 +1,12 @@
-"""The two 3D workgroup tile shapes (64 x 16 and 32 x 32 points in xy).
+"""The 3D workgroup tile shapes: 64 x 16 and 32 x 32 points in xy, and the
+mixed launch (64 x 16 tiles with a last x column of 32 x 32, tile_x 96).
 
 Each point's update is the same sequence of float32 operations whatever
 tile computes it, and source terms are summed per grid point in a fixed
-order, so every result must be bitwise the same under either shape: traces,
+order, so every result must be bitwise the same under every shape: traces,
 final fields, adjoint source traces and gradients, for every storage type.
-The oracle parity of the 32 x 32 shape on its own is covered by the 3D
-parity tests, which run both shapes.
+The oracle parity of each shape on its own is covered by the 3D parity
+tests, which run all three.
 """
 import numpy as np
 import pytest
