@@ -165,7 +165,6 @@ struct WsPlan {
 };
 
 constexpr int kNPart = 512;   // misfit partial sums
-constexpr size_t kCachedField = size_t(128) << 20;   // largest 16-bit field stored with ordinary stores
 constexpr int kFoldEvery = 32;   // adjoint steps per float32 partial gradient sum
 
 size_t side_bytes(int cap, int nc, size_t nptr, size_t off[6], size_t base) {

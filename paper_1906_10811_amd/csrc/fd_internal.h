@@ -15,6 +15,11 @@ constexpr int kTileX = 64;        // x points per 2D tile (16 lanes x 4 points)
 constexpr int kTile2Z = 64;       // z rows per 2D tile
 constexpr int kBlock = 256;       // threads per workgroup
 constexpr int kMaxChunk = 512;    // z planes per 3D workgroup at most
+// Largest field whose new time level a step stores with ordinary stores
+// rather than non-temporal ones (16-bit 3D fields, 2D diffusion fields): a
+// field this small can still sit in the 256 MB memory-side cache when the
+// next step reads it.
+constexpr size_t kCachedField = size_t(128) << 20;
 
 // 3D step tiles have tw4 float4 columns per row: 16 (64 x 16 points) or 8
 // (32 x 32 points); either way one point quad per lane of a workgroup.  A

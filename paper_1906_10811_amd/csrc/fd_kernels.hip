@@ -714,6 +714,7 @@ struct DiffArgs {
     float wx[kMaxR + 1];
     float wz[kMaxR + 1];
     int ntx, ntz;
+    int out_cached;   // ordinary stores of the new level (small fields), else non-temporal
 };
 
 template <int R>
@@ -770,7 +771,11 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d(const DiffArgs a) {
         for (int i = 0; i < 4; ++i) un[i] += xs[4 * HX4 + i];
         const long long off = L.offset(x, 0, z);
         if (nvalid >= 4) {
-            st4nt_f32(a.out + off, make_float4(un[0], un[1], un[2], un[3]));
+            const float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
+            if (a.out_cached)
+                *reinterpret_cast<float4 *>(a.out + off) = r4;
+            else
+                st4nt_f32(a.out + off, r4);
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -899,7 +904,11 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int n
         const int nvalid = L.nx - gx;
         const long long off = L.offset(gx, 0, gz);
         if (nvalid >= 4) {
-            st4nt_f32(a.out + off, make_float4(src[0], src[1], src[2], src[3]));
+            const float4 r4 = make_float4(src[0], src[1], src[2], src[3]);
+            if (a.out_cached)
+                *reinterpret_cast<float4 *>(a.out + off) = r4;
+            else
+                st4nt_f32(a.out + off, r4);
         } else {
             for (int k = 0; k < nvalid; ++k) a.out[off + k] = src[k];
         }
@@ -1246,6 +1255,7 @@ hipError_t launch_diffuse2d(const Layout &L, const float *u, float *out, float w
     }
     a.ntx = (L.nx + kTileX - 1) / kTileX;
     a.ntz = (L.nz + kTile2Z - 1) / kTile2Z;
+    a.out_cached = (size_t)L.elems * sizeof(float) <= kCachedField;
     hipLaunchKernelGGL(f, dim3(a.ntx * a.ntz), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
@@ -1267,6 +1277,7 @@ hipError_t launch_diffuse2d_tb(const Layout &L, const float *u, float *out, floa
     }
     a.ntx = (L.nx + kTileX - 1) / kTileX;
     a.ntz = (L.nz + kTile2Z - 1) / kTile2Z;
+    a.out_cached = (size_t)L.elems * sizeof(float) <= kCachedField;
     hipLaunchKernelGGL(f, dim3(a.ntx * a.ntz), dim3(kBlock), 0, s, a, nlev);
     return hipGetLastError();
 }
