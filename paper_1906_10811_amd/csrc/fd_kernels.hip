@@ -785,8 +785,10 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d(const DiffArgs a) {
 }
 
 // Temporally blocked diffusion: one launch advances `nlev` (<= 16/R) levels.
-// A workgroup stages its 64 x 64 output tile plus an H = R*nlev halo (zero
-// outside the grid) in one LDS buffer and updates it in place level by
+// A workgroup stages its 64 x 64 output tile plus an H = R*nlev halo in z and
+// an H rounded up to a multiple of 4 in x (zero outside the grid; the
+// rounding keeps every staged row and the written tile on 16-byte
+// boundaries at odd H) in one LDS buffer and updates it in place level by
 // level on the shrinking region that stays exact: level t is computed on
 // rows and 4-point groups at least R*t from the staged border (rounded out
 // to whole groups; the rounding margin holds values that nothing exact
@@ -799,14 +801,21 @@ constexpr int kTbPadX = 4;                         // zero floats left/right of 
 constexpr int kTbW4 = (kTileX + 2 * kTbHalo + 2 * kTbPadX) / 4;   // float4 per staged row
 constexpr int kTbPerLane = (kTbRows * kTbW4 + kBlock - 1) / kBlock;   // staged float4 groups per lane
 
+// The LDS buffer (40 KB) allows four workgroups, i.e. four waves per SIMD.
+// At radii 3, 5 and 7 the compiler's own allocation (137-154 VGPRs) allows
+// only three, so those radii are held to four waves per SIMD (97-101 VGPRs,
+// no spills: 5-15 % faster); at the other radii the default allocation
+// already fits four waves, and the same bound made radius 2 slower.
+
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int nlev) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((R & 1) && R > 1 ? 4 : 1))) void k_diffuse2d_tb(const DiffArgs a, int nlev) {
     __shared__ float4 lds[kTbRows * kTbW4];
     const Layout L = a.L;
     const int t0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int bx = t0 % a.ntx, bz = t0 / a.ntx;
-    const int H = R * nlev;                       // staged halo of this launch
-    const int x0 = bx * kTileX - H, z0 = bz * kTile2Z - H;   // grid coords of staged (0, 0)
+    const int H = R * nlev;                       // staged halo of this launch in z
+    const int Hx = (H + 3) & ~3;                  // and in x, whole float4 groups
+    const int x0 = bx * kTileX - Hx, z0 = bz * kTile2Z - H;   // grid coords of staged (0, 0)
     const int rows = kTile2Z + 2 * H;
     const int g4 = kTbW4;                         // staged float4 per row: the full LDS row, so every
                                                   // neighbour group a level reads holds grid data or zero
@@ -844,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int n
         // level t region: rows [R t, rows - R t), float4 columns [c0, c1)
         const int r0 = R * t, r1 = rows - R * t;
         const int c0 = 1 + (R * t) / 4;                        // first float4 column (pad column is 0)
-        const int c1 = 1 + (kTileX + 2 * H - R * t + 3) / 4;   // one past the last
+        const int c1 = 1 + (kTileX + 2 * Hx - R * t + 3) / 4;  // one past the last
         float4 res[kTbPerLane];
 #pragma unroll
         for (int k = 0; k < kTbPerLane; ++k) {
@@ -898,13 +907,14 @@ __global__ __launch_bounds__(kBlock) void k_diffuse2d_tb(const DiffArgs a, int n
     // write the 64 x 64 tile
     for (int i = lane; i < kTile2Z * (kTileX / 4); i += kBlock) {
         const int lr = i / (kTileX / 4), cq = i - lr * (kTileX / 4);
-        const int gz = z0 + H + lr, gx = x0 + H + 4 * cq;
+        const int gz = z0 + H + lr, gx = x0 + Hx + 4 * cq;
         if (gz >= L.nz || gx >= L.nx) continue;
-        const float *src = ldsf + (H + lr) * kTbW4 * 4 + kTbPadX + H + 4 * cq;
+        const int c = (kTbPadX + Hx) / 4 + cq;         // float4 column of the written group
+        const float *src = ldsf + ((H + lr) * kTbW4 + c) * 4;
         const int nvalid = L.nx - gx;
         const long long off = L.offset(gx, 0, gz);
         if (nvalid >= 4) {
-            const float4 r4 = make_float4(src[0], src[1], src[2], src[3]);
+            const float4 r4 = lds[(H + lr) * kTbW4 + c];
             if (a.out_cached)
                 *reinterpret_cast<float4 *>(a.out + off) = r4;
             else
