@@ -22,9 +22,9 @@ listed with its pin in the design notes:
   O2 medium      v on the padded grid, layer filled by edge replication.
   O3 weights     maximal-order central 2nd-derivative weights, r = so/2.
   O4 Laplacian   sum over axes, zero outside the padded grid.
-  O5 damping     sigma = sigma_max sum_a (d_a / nbl)^2  (parity unpinned:
-                 the profile itself has no pin, only invariants that hold
-                 for any sigma >= 0).
+  O5 damping     sigma = sigma_max sum_a (d_a / nbl)^2; the default
+                 sigma_max is pinned by the measured round-trip reflection
+                 of the layer.
   O6 update      centred leapfrog with centred damping.
   O7 time step   Courant number v_max dt / h.
   O8 sources     multilinear weights over the 2^d cell corners, / prod(h).
@@ -171,7 +171,9 @@ def fd_weights(space_order: int) -> np.ndarray:
 # O2 / O5 / O7: medium, damping, time step
 # --------------------------------------------------------------------------
 def pad_velocity(g: Grid, v_phys) -> np.ndarray:
-    """O2: widen to float64 and fill the damping layer by edge replication."""
+    """O2: widen to float64 and fill the damping layer by edge replication:
+    a layer point takes the velocity of the nearest physical point (pinned by
+    a brute-force nearest-point search)."""
     v = np.asarray(v_phys, dtype=np.float64)
     if v.shape != tuple(reversed(g.shape)):
         raise ValueError("velocity shape %s != %s" % (v.shape, tuple(reversed(g.shape))))
@@ -181,9 +183,13 @@ def pad_velocity(g: Grid, v_phys) -> np.ndarray:
 
 
 def sigma_max_default(g: Grid, vmax: float) -> float:
-    """O5 default: 3 v_max ln(1000) / (2 nbl h), h the smallest spacing.
-    Parity unpinned: the thesis describes no absorbing layer; this value is a
-    reading, checked only through invariants that hold for any sigma >= 0."""
+    """O5 default: 3 v_max ln(1000) / (2 nbl h), h the smallest spacing --
+    the estimate that gives a perfectly matched layer of quadratic profile a
+    round-trip reflection of 1e-3.  With the damping term m sigma u_t of this
+    PDE, a wave of frequency w >> sigma decays as exp(-x sigma / (2 v)), half
+    the PML rate, so the same sigma_max returns 1000^(-1/2) of a normally
+    incident wave at v_max after a round trip through a thick layer (pinned
+    by a measured reflection; the thesis describes no absorbing layer)."""
     if g.nbl == 0:
         return 0.0
     return 3.0 * vmax * math.log(1000.0) / (2.0 * g.nbl * min(g.spacing))
@@ -192,9 +198,9 @@ def sigma_max_default(g: Grid, vmax: float) -> float:
 def damping(g: Grid, sigma_max: float) -> np.ndarray:
     """O5: sigma_i = sigma_max sum_a (d_a / nbl)^2 with
     d_a = max(0, nbl - i_a, i_a - (nbl + N_a - 1)); zero when nbl == 0.
-    Parity unpinned: no passage of the thesis fixes the profile; the pins
-    that cover it (energy non-increasing, reciprocity, adjoint identity,
-    gradient in the layer) hold for any non-negative profile."""
+    No passage of the thesis fixes the profile.  Pinned by hand values, and
+    through the measured round-trip reflection, which depends on the sum of
+    sigma over the layer (a linear or cubic profile fails it)."""
     sig = np.zeros(g.array_shape, dtype=np.float64)
     if g.nbl == 0:
         return sig
