@@ -186,6 +186,15 @@ int fd_forward(fd_grid *grid, const fd_shot *shot, int nt, double dt,
  * receives (F^T r)_s[n] = dt^2/prod(h) sum_c W_s,c lambda^n.  The same step
  * kernel runs with the roles of sources and receivers exchanged.  Errors as
  * for fd_forward.
+ *
+ * The thesis motivates its stencil work by seismic inversion (Chapter 1,
+ * Section 2.1), which needs this adjoint of the modelling operator; it
+ * gives no formula for it.  The reading here is discretise-then-transpose:
+ * starting from lambda^{nt} = lambda^{nt+1} = 0, for k = nt .. 1,
+ *   lambda^{k-1} = [2 lambda^k - (1 - sigma dt/2) lambda^{k+1}
+ *                   + dt^2 v^2 Lap_h lambda^k + v^2 P_r^T r^{k-1}] / (1 + sigma dt/2),
+ * the exact transpose of the forward recursion, sources and receivers
+ * above, so <F w, r> = <w, F^T r> holds to rounding.
  */
 int fd_adjoint(fd_grid *grid, const fd_shot *shot, int nt, double dt,
                const float *residual_dev, float *src_adj_dev, void *stream);
@@ -194,6 +203,9 @@ int fd_adjoint(fd_grid *grid, const fd_shot *shot, int nt, double dt,
 #define FD_GRAD_RESIDUAL_GIVEN 1   /* d_obs_dev holds the residual itself */
 #define FD_GRAD_BINOMIAL 2         /* checkpoint_every is a number of snapshot slots (>= 0);
                                       the reverse sweep follows fd_checkpoint_schedule */
+#define FD_GRAD_VELOCITY 4         /* grad_m_dev receives the gradient with respect to the
+                                      velocity, g_v = g_m dm/dv = -2 g_m / v^3, with v the
+                                      grid's padded velocity (sigma held fixed) */
 
 /* Device workspace for fd_gradient.  Default: checkpoints of (u^c, u^{c-1})
  * every checkpoint_every steps except the last segment's (ceil(nt /
@@ -234,8 +246,13 @@ int fd_checkpoint_schedule(int nt, int slots, fd_ckpt_action *actions, int capac
                            int *n_actions, long long *forward_steps);
 
 /*
- * Misfit and gradient with respect to m = 1/v^2 on the padded grid (both
- * checkpointing modes give bitwise the same result):
+ * Misfit and gradient for seismic inversion, the application the thesis's
+ * stencil work serves (Chapter 1, Section 2.1); the thesis states neither
+ * the misfit nor the imaging condition, so the reading is the exact
+ * derivative of the discrete forward map above (discretise-then-
+ * differentiate).  Gradient with respect to m = 1/v^2 on the padded grid
+ * (or v with FD_GRAD_VELOCITY), sigma held fixed (all checkpointing modes
+ * give bitwise the same result):
  *   J = 1/2 sum_n sum_r (rec_r[n] - d_obs_r[n])^2
  *   g_m = - sum_n lambda^n [(u^{n+1} - 2u^n + u^{n-1}) + (sigma dt/2)(u^{n+1} - u^{n-1})]
  * with lambda the adjoint field driven by the residual.  The bracket of each
@@ -247,7 +264,12 @@ int fd_checkpoint_schedule(int nt, int slots, fd_ckpt_action *actions, int capac
  * (the residual itself when flags has FD_GRAD_RESIDUAL_GIVEN).
  * misfit_dev: device double[1]; grad_m_dev: device double, dense padded;
  * rec_out (nullable): device float32 [nt][nrec]; src_adj (nullable): device
- * float32 [nt][nsrc] receives F^T of the residual.
+ * float32 [nt][nsrc] receives F^T of the residual.  workspace: device, at
+ * least fd_gradient_workspace_bytes for the same (nt, nrec,
+ * checkpoint_every, flags), 256-byte aligned, borrowed for the call's
+ * enqueued work.  Errors: FD_ERR_ARG for an unknown flag, a null required
+ * pointer or a 16-bit grid; FD_ERR_NOMEM for a short workspace; otherwise
+ * as for fd_forward.
  */
 int fd_gradient(fd_grid *grid, const fd_shot *shot, int nt, double dt,
                 const float *d_obs_dev, int checkpoint_every, int flags,

@@ -189,11 +189,13 @@ class Grid:
 
     def gradient(self, src_xyz, wavelet: torch.Tensor, rec_xyz, d_obs: torch.Tensor, dt: float,
                  checkpoint_every: int = 50, residual_given: bool = False, want_src_adj: bool = False,
-                 binomial_slots: int | None = None, stream=None):
+                 binomial_slots: int | None = None, wrt_velocity: bool = False, stream=None):
         """fd_gradient.  Returns (misfit [1] float64, g_m dense padded float64,
         traces [nt, nrec], F^T residual [nt, nsrc] or None).  binomial_slots
-        > 0 selects the binomial checkpoint schedule with that many snapshot
-        slots (0 allowed) instead of checkpoints every checkpoint_every steps."""
+        not None selects the binomial checkpoint schedule with that many
+        snapshot slots (0 allowed) instead of checkpoints every
+        checkpoint_every steps.  wrt_velocity: the gradient with respect to
+        the padded velocity instead of m (FD_GRAD_VELOCITY)."""
         lib = _lib.load()
         wav = _dev_f32(wavelet, "wavelet")
         if wav.dim() == 1:
@@ -202,6 +204,8 @@ class Grid:
         nt = obs.shape[0]
         sh, keep = self._shot(src_xyz, wav, rec_xyz)
         flags = _lib.FD_GRAD_RESIDUAL_GIVEN if residual_given else 0
+        if wrt_velocity:
+            flags |= _lib.FD_GRAD_VELOCITY
         K = int(checkpoint_every)
         if binomial_slots is not None:
             flags |= _lib.FD_GRAD_BINOMIAL
@@ -233,42 +237,49 @@ class Grid:
 class _Modeling(torch.autograd.Function):
     """Traces as a differentiable function of the padded velocity and the
     source wavelets; the backward pass is fd_gradient driven by the incoming
-    trace cotangent (m = 1/v^2, dm/dv = -2/v^3)."""
+    trace cotangent, which also applies the chain rule from m = 1/v^2 to v
+    (FD_GRAD_VELOCITY).  The damping strength is a constant of the operator:
+    the forward grid's sigma_max (given, or the library's default from that
+    grid's v_max) is passed unchanged to the backward grid, so the gradient
+    is the derivative of the forward map with sigma fixed."""
 
     @staticmethod
     def forward(ctx, vp_padded, wavelet, shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt,
-                checkpoint_every, sinc_radius):
+                checkpoint_every, sinc_radius, damp_max):
         g = Grid(shape, spacing, vp_padded, space_order=space_order, nbl=nbl, vp_padded=True,
-                 sinc_radius=sinc_radius)
+                 sinc_radius=sinc_radius, damp_max=damp_max)
         rec = g.forward(src_xyz, wavelet, rec_xyz, dt)
         ctx.save_for_backward(vp_padded, wavelet)
-        ctx.cfg = (shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, checkpoint_every, sinc_radius)
+        ctx.cfg = (shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, checkpoint_every, sinc_radius,
+                   g.damp_max)
         g.close()
         return rec
 
     @staticmethod
     def backward(ctx, grad_rec):
         vp_padded, wavelet = ctx.saved_tensors
-        shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, K, sinc_radius = ctx.cfg
+        shape, spacing, space_order, nbl, src_xyz, rec_xyz, dt, K, sinc_radius, damp_max = ctx.cfg
         g = Grid(shape, spacing, vp_padded, space_order=space_order, nbl=nbl, vp_padded=True,
-                 sinc_radius=sinc_radius)
-        _, g_m, _, g_w = g.gradient(src_xyz, wavelet, rec_xyz, grad_rec.contiguous(), dt,
-                                    checkpoint_every=K, residual_given=True, want_src_adj=True)
+                 sinc_radius=sinc_radius, damp_max=damp_max)
+        _, g_v, _, g_w = g.gradient(src_xyz, wavelet, rec_xyz, grad_rec.contiguous(), dt,
+                                    checkpoint_every=K, residual_given=True, want_src_adj=True,
+                                    wrt_velocity=True)
         torch.cuda.current_stream().synchronize()
         g.close()
-        v = vp_padded.to(torch.float64)
-        g_v = (g_m * (-2.0 / v ** 3)).to(vp_padded.dtype)
-        return g_v, g_w.to(wavelet.dtype).reshape(wavelet.shape), None, None, None, None, None, None, None, None, None
+        return (g_v.to(vp_padded.dtype), g_w.to(wavelet.dtype).reshape(wavelet.shape),
+                None, None, None, None, None, None, None, None, None, None)
 
 
 def modeling(vp_padded: torch.Tensor, wavelet: torch.Tensor, shape, spacing, space_order: int,
              nbl: int, src_xyz, rec_xyz, dt: float, checkpoint_every: int = 50,
-             sinc_radius: int = 0) -> torch.Tensor:
+             sinc_radius: int = 0, damp_max: float = 0.0) -> torch.Tensor:
     """Differentiable forward modelling: traces [nt, nrec] from the velocity
     on the padded grid and the wavelets [nt, nsrc] (sparse points multilinear,
-    or windowed sinc of the given half-width)."""
+    or windowed sinc of the given half-width).  damp_max: sigma_max of the
+    damping layer, 1/s; <= 0 takes the library's default from max(v) at the
+    forward call.  Either way sigma is held fixed in the gradient."""
     return _Modeling.apply(vp_padded, wavelet, tuple(shape), tuple(spacing), space_order, nbl,
-                           src_xyz, rec_xyz, dt, checkpoint_every, int(sinc_radius))
+                           src_xyz, rec_xyz, dt, checkpoint_every, int(sinc_radius), float(damp_max))
 
 
 class Server:

@@ -24,6 +24,7 @@ FD_STORE_BF16 = 2
 
 FD_GRAD_RESIDUAL_GIVEN = 1
 FD_GRAD_BINOMIAL = 2
+FD_GRAD_VELOCITY = 4
 
 FD_ACT_ADVANCE, FD_ACT_STORE, FD_ACT_RESTORE, FD_ACT_YOUTURN = 1, 2, 3, 4
 

@@ -73,10 +73,12 @@ struct DeviceGuard {
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
+}  // namespace
+
 // Maximal-order central second-derivative weights, radius r:
 // c_j = 2 (-1)^(j+1) (r!)^2 / (j^2 (r-j)! (r+j)!), c_0 = -2 sum c_j.
 // All factorials up to 16! are exact in double.
-void second_derivative_weights(int r, double *c) {
+void fdi_second_derivative_weights(int r, double *c) {
     auto fact = [](int n) {
         double f = 1.0;
         for (int i = 2; i <= n; ++i) f *= i;
@@ -90,8 +92,6 @@ void second_derivative_weights(int r, double *c) {
     }
     c[0] = -2.0 * sum;
 }
-
-}  // namespace
 
 // ----------------------------------------------------------- grid plumbing
 bool fdi_check_desc(const fd_grid_desc *d) {
@@ -669,7 +669,7 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     g->amp = (desc->storage != FD_STORE_F32 && desc->amp_scale > 0.f) ? desc->amp_scale : 1.f;
     g->auto_amp = desc->storage == FD_STORE_F16 && !(desc->amp_scale > 0.f);
     g->nc = sparse_nodes(desc);
-    second_derivative_weights(L.r, g->c);
+    fdi_second_derivative_weights(L.r, g->c);
     g->cell = 1.0;
     for (int a = 0; a < desc->ndim; ++a) g->cell *= desc->spacing[a];
     g->ws = (char *)workspace;
@@ -1029,6 +1029,8 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     if ((rc = check_dt(g, dt, nt))) return rc;
     if (nt < 1 || K < ((flags & FD_GRAD_BINOMIAL) ? 0 : 1))
         return fdi_fail(FD_ERR_ARG, "nt >= 1; checkpoint_every >= 1 (>= 0 snapshot slots when binomial)");
+    if (flags & ~(FD_GRAD_RESIDUAL_GIVEN | FD_GRAD_BINOMIAL | FD_GRAD_VELOCITY))
+        return fdi_fail(FD_ERR_ARG, "unknown fd_gradient flag");
     if (g->st != Store::F32) return fdi_fail(FD_ERR_ARG, "fd_gradient needs float32 storage");
     if (!d_obs || !misfit || !grad_m || !workspace || !sh->src_wavelet)
         return fdi_fail(FD_ERR_ARG, "null pointer argument");
@@ -1188,8 +1190,14 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
         int cu = 0, cp = 1;   // pool fields of (u^n, u^{n-1})
         // Every pool field is zeroed once: a step writes only the grid points
         // of its output, so the zero halo that realises the zero extension
-        // must already be there in whichever field it writes.
+        // must already be there in whichever field it writes.  So is the
+        // out-of-place output of the bracket step, which the last trace row
+        // samples (a windowed-sinc node outside the grid reads its zero
+        // column with weight 0, and 0 times a stale NaN is NaN), and the
+        // bracket field.
         for (int i = 0; i < npool; ++i) HIPCHK(launch_zero_field(L, pool[i], g->st, s));
+        HIPCHK(launch_zero_field(L, out_f, g->st, s));
+        HIPCHK(launch_zero_field(L, brf, Store::F32, s));
         HIPCHK(launch_zero_field(L, g->uA, g->st, s));
         HIPCHK(launch_zero_field(L, g->uB, g->st, s));
         slot_u[0] = cu;
@@ -1258,7 +1266,7 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
         }
     }
     if (adj_done % kFoldEvery) HIPCHK(launch_fold_f64(L, gacc, gpart, s));
-    HIPCHK(launch_field_to_dense_f64(L, gacc, grad_m, s));
+    HIPCHK(launch_field_to_dense_f64(L, gacc, (flags & FD_GRAD_VELOCITY) ? g->vel : nullptr, grad_m, s));
     if (src_adj) {
         Sample sm = make_sample(g, 0, sh->nsrc, src_adj, adj_smp);
         HIPCHK(launch_sample(sm, LA, g->st, s));

@@ -11,6 +11,8 @@ int fdi_fail(int code, const char *fmt, ...);
 bool fdi_check_desc(const fd_grid_desc *d);
 // Device layout of one field of a grid.
 fd::Layout fdi_layout(const fd_grid_desc *d);
+// Maximal-order central second-derivative weights c_0..c_r of radius r.
+void fdi_second_derivative_weights(int r, double *c);
 
 // Chunked forward modelling, used by fd_forward, fd_gradient and the server.
 int fdi_forward_prepare(fd_grid *g, const fd_shot *sh, int nt, double dt, hipStream_t s);

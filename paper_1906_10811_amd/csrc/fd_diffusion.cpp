@@ -34,21 +34,6 @@ bool to_grid_desc(const fd_diffusion_desc *d, fd_grid_desc *g) {
     return fdi_check_desc(g);
 }
 
-// c_j of the maximal-order central second derivative, radius r.
-void weights(int r, double *c) {
-    auto fact = [](int n) {
-        double f = 1.0;
-        for (int i = 2; i <= n; ++i) f *= i;
-        return f;
-    };
-    double sum = 0.0;
-    for (int j = 1; j <= r; ++j) {
-        c[j] = 2.0 * ((j % 2) ? 1.0 : -1.0) * fact(r) * fact(r) / ((double)j * j * fact(r - j) * fact(r + j));
-        sum += c[j];
-    }
-    c[0] = -2.0 * sum;
-}
-
 }  // namespace
 
 extern "C" int fd_diffusion_workspace_bytes(const fd_diffusion_desc *desc, size_t *bytes) {
@@ -60,8 +45,9 @@ extern "C" int fd_diffusion_workspace_bytes(const fd_diffusion_desc *desc, size_
     return FD_OK;
 }
 
-extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, size_t ws_bytes,
-                                const float *u0, float *u_out, int nt, double dt, void *stream) {
+namespace {
+int run_diffusion(const fd_diffusion_desc *desc, void *workspace, size_t ws_bytes, const float *u0,
+                  float *u_out, int nt, double dt, void *stream) {
     fd_grid_desc g;
     if (!to_grid_desc(desc, &g)) return FD_ERR_ARG;
     if (!workspace || !u0 || !u_out) return fdi_fail(FD_ERR_ARG, "null pointer argument");
@@ -71,7 +57,7 @@ extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, 
     const size_t fb = align_up(sizeof(float) * (size_t)L.elems, 256);
     if (ws_bytes < 2 * fb) return fdi_fail(FD_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, 2 * fb);
     double c[kMaxR + 1];
-    weights(L.r, c);
+    fdi_second_derivative_weights(L.r, c);
     double s_odd = 0.0;
     for (int j = 1; j <= L.r; j += 2) s_odd += c[j];
     const double hx2 = desc->spacing[0] * desc->spacing[0], hy2 = desc->spacing[1] * desc->spacing[1];
@@ -115,4 +101,10 @@ extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, 
     if ((e = launch_field_to_dense(L, A, u_out, Store::F32, 1.f, s)) != hipSuccess)
         return fdi_fail(FD_ERR_DEVICE, "diffusion readback: %s", hipGetErrorString(e));
     return FD_OK;
+}
+}  // namespace
+
+extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, size_t ws_bytes,
+                                const float *u0, float *u_out, int nt, double dt, void *stream) {
+    return run_diffusion(desc, workspace, ws_bytes, u0, u_out, nt, dt, stream);
 }

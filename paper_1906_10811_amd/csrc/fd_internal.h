@@ -155,6 +155,9 @@ hipError_t launch_zero_f64(double *p, long long n, hipStream_t s);
 // acc += part; part = 0 over the grid rows of two pitched fields of layout L
 // (float64 and float32); halo and pad cells are not touched.
 hipError_t launch_fold_f64(const Layout &L, double *acc, float *part, hipStream_t s);
-hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, double *dense, hipStream_t s);
+// Dense copy of a pitched float64 field; with vel (pitched float32
+// velocity, nullable) each value is multiplied by -2 / v^3 in float64.
+hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, const float *vel, double *dense,
+                                     hipStream_t s);
 
 }  // namespace fd

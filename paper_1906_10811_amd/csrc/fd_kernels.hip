@@ -1232,21 +1232,30 @@ hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, S
 }
 
 namespace {
-__global__ void k_field_to_dense_f64(const Layout L, const double *f, double *dense) {
+// dense = f, or with a velocity field the chain rule from m = 1/v^2 to v:
+// dense = f * dm/dv = f * (-2 / v^3), in float64.
+__global__ void k_field_to_dense_f64(const Layout L, const double *f, const float *vel, double *dense) {
     const long long n = (long long)L.nx * L.ny * L.nz;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % L.nx);
         const int y = (int)((i / L.nx) % L.ny);
         const int z = (int)(i / ((long long)L.nx * L.ny));
-        dense[i] = f[L.offset(x, y, z)];
+        const long long o = L.offset(x, y, z);
+        double g = f[o];
+        if (vel) {
+            const double v = (double)vel[o];
+            g *= -2.0 / (v * v * v);
+        }
+        dense[i] = g;
     }
 }
 }  // namespace
 
-hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, double *dense, hipStream_t s) {
+hipError_t launch_field_to_dense_f64(const Layout &L, const double *f, const float *vel, double *dense,
+                                     hipStream_t s) {
     const long long n = (long long)L.nx * L.ny * L.nz;
-    hipLaunchKernelGGL(k_field_to_dense_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, L, f, dense);
+    hipLaunchKernelGGL(k_field_to_dense_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, L, f, vel, dense);
     return hipGetLastError();
 }
 

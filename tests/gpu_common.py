@@ -20,6 +20,50 @@ def rel_l2(got, want) -> float:
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
+# Element-wise bars beside the global relative L2 gate.  Per receiver the
+# error is taken relative to that receiver's own norm, or to a tenth of the
+# strongest receiver's norm when it is weaker (float32 rounding travels with
+# the wavefield, so a receiver the wave barely reaches carries errors of the
+# field's scale, not its own); K_REC times the gate.  Per field the largest
+# pointwise error is taken relative to the field's largest magnitude, K_ABS
+# times the gate.
+K_REC = 3.0
+K_ABS = 3.0
+
+
+def trace_errors(got, want):
+    """(global relative L2, worst per-receiver relative L2 as defined above)
+    of traces [nt, nrec]."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    norms = np.linalg.norm(want, axis=0)
+    per = np.linalg.norm(got - want, axis=0) / np.maximum(norms, 0.1 * norms.max())
+    return rel_l2(got, want), float(per.max())
+
+
+def field_errors(got, want):
+    """(global relative L2, max |got - want| / max |want|) of a field."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    return rel_l2(got, want), float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+
+
+def assert_traces(got, want, tol=1e-5, label=""):
+    e, per = trace_errors(got, want)
+    print("%s traces: rel_l2 %.3e, worst receiver %.3e" % (label, e, per), flush=True)
+    assert e <= tol, (label, e)
+    assert per <= K_REC * tol, (label, per)
+    return e, per
+
+
+def assert_field(got, want, tol=1e-5, label=""):
+    e, m = field_errors(got, want)
+    print("%s field: rel_l2 %.3e, max-abs %.3e" % (label, e, m), flush=True)
+    assert e <= tol, (label, e)
+    assert m <= K_ABS * tol, (label, m)
+    return e, m
+
+
 def case(shape, so, nbl, nt, seed=0, nsrc=1, nrec=7, h=(10.0, 12.0, 9.0), f0=None, model="random"):
     """A heterogeneous, damped case with off-grid sources and receivers."""
     ndim = len(shape)

@@ -21,7 +21,7 @@ def _hat(nx, ny, seed):
     return u + 0.05 * rng.standard_normal((ny, nx))
 
 
-@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 16])
+@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16])
 @pytest.mark.parametrize("time_block", [0, 1, 3, 16])
 def test_diffusion_parity(so, time_block):
     """203 x 141 (ragged 64 x 64 tiles), 121 steps: the automatic choice, one
