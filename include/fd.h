@@ -366,6 +366,21 @@ int fd_diffusion_workspace_bytes(const fd_diffusion_desc *desc, size_t *bytes);
 int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, size_t ws_bytes,
                      const float *u0_dev, float *u_out_dev, int nt, double dt, void *stream);
 
+/*
+ * fd_diffusion_run without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the two fields live in a static device
+ * array of 64 MiB inside the library, one per GPU, held until the process
+ * ends; nothing is allocated or freed.  Grids whose two pitched fields
+ * exceed it (beyond about 2800 x 2800) give FD_ERR_NOMEM.  Every call on a
+ * GPU uses that GPU's one array: the call clears it before use, and calls
+ * that overlap in time on one GPU (two streams, two threads) race -- order
+ * them.  The first call on a device resolves the array's address there.
+ * Arguments, result and errors otherwise as fd_diffusion_run.
+ */
+int fd_diffusion_run_noalloc(const fd_diffusion_desc *desc, const float *u0_dev, float *u_out_dev, int nt,
+                             double dt, void *stream);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *fd_last_error(void);
 

@@ -108,3 +108,21 @@ extern "C" int fd_diffusion_run(const fd_diffusion_desc *desc, void *workspace, 
                                 const float *u0, float *u_out, int nt, double dt, void *stream) {
     return run_diffusion(desc, workspace, ws_bytes, u0, u_out, nt, dt, stream);
 }
+
+extern "C" int fd_diffusion_run_noalloc(const fd_diffusion_desc *desc, const float *u0, float *u_out, int nt,
+                                        double dt, void *stream) {
+    fd_grid_desc g;
+    if (!to_grid_desc(desc, &g)) return FD_ERR_ARG;
+    const Layout L = fdi_layout(&g);
+    const size_t need = 2 * align_up(sizeof(float) * (size_t)L.elems, 256);
+    if (need > kStaticScratchBytes)
+        return fdi_fail(FD_ERR_NOMEM, "grid needs %zu scratch bytes, above the static maximum of %zu", need,
+                        kStaticScratchBytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fdi_fail(FD_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    void *ws = nullptr;
+    if ((e = static_scratch(dev, &ws)) != hipSuccess)
+        return fdi_fail(FD_ERR_DEVICE, "static scratch of device %d: %s", dev, hipGetErrorString(e));
+    return run_diffusion(desc, ws, kStaticScratchBytes, u0, u_out, nt, dt, stream);
+}

@@ -20,6 +20,9 @@ constexpr int kMaxChunk = 512;    // z planes per 3D workgroup at most
 // field this small can still sit in the 256 MB memory-side cache when the
 // next step reads it.
 constexpr size_t kCachedField = size_t(128) << 20;
+// Bytes of the static device scratch behind fd_diffusion_run_noalloc (two
+// pitched float32 fields: a 2500 x 2500 grid at every space order).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 
 // 3D step tiles have tw4 float4 columns per row: 16 (64 x 16 points) or 8
 // (32 x 32 points); either way one point quad per lane of a workgroup.  A
@@ -149,6 +152,10 @@ hipError_t launch_diffuse2d(const Layout &L, const float *u, float *out, float w
 int diffuse2d_max_levels(int r);
 hipError_t launch_diffuse2d_tb(const Layout &L, const float *u, float *out, float w0, const float *wx,
                                const float *wz, int nlev, hipStream_t s);
+// Address of the static scratch (kStaticScratchBytes) on `device`, which
+// must be the current device; resolved with hipGetSymbolAddress on the
+// first call per device and kept.
+hipError_t static_scratch(int device, void **ptr);
 hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
                          float *resid, double *partials, int npart, double *out, hipStream_t s);
 hipError_t launch_zero_f64(double *p, long long n, hipStream_t s);

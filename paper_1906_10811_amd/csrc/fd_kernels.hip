@@ -25,7 +25,14 @@
 
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
+
+// Device scratch of the allocation-free diffusion entry point: a fixed
+// array in the code object, one copy per GPU, reached from host code only
+// through the address hipGetSymbolAddress returns for the current device
+// (see fd::static_scratch); the name itself is not a device address there.
+static __device__ __align__(256) unsigned char scratch[fd::kStaticScratchBytes];
 
 namespace fd {
 namespace {
@@ -1299,6 +1306,26 @@ hipError_t launch_diffuse2d_tb(const Layout &L, const float *u, float *out, floa
     a.out_cached = (size_t)L.elems * sizeof(float) <= kCachedField;
     hipLaunchKernelGGL(f, dim3(a.ntx * a.ntz), dim3(kBlock), 0, s, a, nlev);
     return hipGetLastError();
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t static_scratch(int device, void **ptr) {
+    if (device < 0 || device >= kMaxDevices || !ptr) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_misfit(const float *rec, const float *obs, long long n, int residual_given,
