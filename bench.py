@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-B_STEP = 16.0          # algorithmic bytes per point and step, float32 wavefields
+B_STEP = 16.0          # algorithmic bytes per point and step, float32 wavefields, one step per launch
+B_STEP2 = 10.0         # ... two leapfrog levels per launch (20 B per point and launch)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_10811_amd", "csrc", f)
                for f in ("fd_kernels.hip", "fd_internal.h", "fd_api.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step3d_so8_layered336.txt")
@@ -94,21 +95,29 @@ def time_forward(torch, g, w, wav, steps, warmup, stream):
     return e0.elapsed_time(e1) / 1000.0, rec
 
 
-def bench_headline(torch, dev, steps, warmup, stream):
+def bench_headline(torch, dev, steps, warmup, stream, time_block=0):
+    """The layered3d_256 forward.  With two leapfrog levels per launch (the
+    automatic choice) a launch advances two time steps and moves 20 B per
+    point (u^n, u^{n-1}, p in; u^{n+1}, u^{n+2} out), 10 per point-step; one
+    step per launch moves 16."""
     from paper_1906_10811_amd import Grid
     w, v, wav = make_workload("layered3d_256", torch, dev)
     g = Grid(w["shape"], w["spacing"], v, space_order=w["space_order"], nbl=w["nbl"], origin=w["origin"],
-             stream=stream)
+             time_block=time_block, stream=stream)
     secs, rec = time_forward(torch, g, w, wav, steps, warmup, stream)
     pts = g.padded_points
     nt = w["nt"]
+    tb = g.time_block
+    b_step = B_STEP2 if tb == 2 else B_STEP
+    launches = nt // tb + nt % tb
     gpts = pts * nt * steps / secs / 1e9
     interior = math.prod(w["shape"]) * nt * steps / secs / 1e9
-    launch_s = secs / (steps * nt)
-    achieved = B_STEP * pts / launch_s / 1e9
-    traffic = stored_traffic()
+    launch_s = secs / (steps * launches)
+    achieved = b_step * tb * pts / launch_s / 1e9
+    traffic = stored_traffic() if tb == 2 else None
     out = dict(gpts=gpts, interior=interior, ms_per_step=secs / steps * 1000.0, launch_us=launch_s * 1e6,
-               achieved=achieved, traffic=traffic, pts=pts, rec_norm=float(rec.norm().item()))
+               achieved=achieved, traffic=traffic, pts=pts, rec=rec.cpu().numpy(), time_block=tb, b_step=b_step,
+               zchunk=g.zchunk)
     g.close()
     return w, out
 
@@ -133,15 +142,24 @@ def copy_probe(torch, dev, stream, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / secs / 1e9
 
 
-def bench_cpu_baseline(w):
-    """The FP64 oracle as it stands, on the host cores, over a bounded
-    sample: the same grid and medium, the first `nt` time steps."""
+def _oracle_setup(w, v):
     import oracle
     og = oracle.Grid(tuple(w["shape"]), tuple(w["spacing"]), tuple(w["origin"]), w["space_order"], w["nbl"])
-    v = synth.velocity(w)
     vp = oracle.pad_velocity(og, v)
     sig = oracle.damping(og, oracle.sigma_max_default(og, float(vp.max())))
-    wav = synth.wavelets(w).astype(np.float64)
+    return og, vp, sig, synth.wavelets(w).astype(np.float64)
+
+
+def bench_cpu_baseline(w, grf=None):
+    """The FP64 oracle as it stands, on the host cores, over bounded samples:
+    the headline grid and medium for the first time steps that take about
+    15 s on all cores (its traces are also the FP64 reference the GPU traces
+    of those steps are compared with), a few steps of the same on one core,
+    and (grf = (workload, velocity)) the first 100 steps of grf3d_512."""
+    import oracle
+    og, vp, sig, wav = _oracle_setup(w, synth.velocity(w))
+    pts = math.prod(og.padded)
+    cores = oracle.num_threads()
     nt = 2
     t0 = time.perf_counter()
     oracle.forward(og, vp, sig, w["dt"], nt, w["src"], wav[:nt], w["rec"])
@@ -149,12 +167,40 @@ def bench_cpu_baseline(w):
     # scale to about 15 s of work (the 2-step probe overestimates a step)
     nt2 = max(2, min(1000, int(24.0 / max(1e-3, (t1 - t0) / nt))))
     t0 = time.perf_counter()
-    oracle.forward(og, vp, sig, w["dt"], nt2, w["src"], wav[:nt2], w["rec"])
+    rec, *_ = oracle.forward(og, vp, sig, w["dt"], nt2, w["src"], wav[:nt2], w["rec"])
     t1 = time.perf_counter()
-    pts = math.prod(og.padded)
-    return dict(value=pts * nt2 / (t1 - t0) / 1e9, unit="Gpts/s", cores=oracle.num_threads(), kind="oracle",
-                sample="layered3d_256 grid (336^3 padded, so 8, FP64), first %d of 1000 time steps, %.1f s"
-                % (nt2, t1 - t0))
+    out = dict(value=pts * nt2 / (t1 - t0) / 1e9, unit="Gpts/s", cores=cores, kind="oracle",
+               sample="layered3d_256 grid (336^3 padded, so 8, FP64), first %d of 1000 time steps, %.1f s"
+               % (nt2, t1 - t0))
+    oracle.set_num_threads(1)
+    one = oracle.num_threads()
+    n1 = 4
+    t0 = time.perf_counter()
+    oracle.forward(og, vp, sig, w["dt"], n1, w["src"], wav[:n1], w["rec"])
+    t1 = time.perf_counter()
+    oracle.set_num_threads(cores)
+    out["single_core"] = dict(value=pts * n1 / (t1 - t0) / 1e9, cores=one,
+                              sample="layered3d_256 grid, first %d time steps on one core, %.1f s" % (n1, t1 - t0))
+    del vp, sig
+    grf_rec = None
+    if grf is not None:
+        wg, vg = grf
+        og, vp, sig, wav = _oracle_setup(wg, vg)
+        n3 = 100
+        t0 = time.perf_counter()
+        grf_rec, *_ = oracle.forward(og, vp, sig, wg["dt"], n3, wg["src"], wav[:n3], wg["rec"])
+        t1 = time.perf_counter()
+        out["grf3d_512_slice"] = dict(value=math.prod(og.padded) * n3 / (t1 - t0) / 1e9, cores=cores,
+                                      sample="grf3d_512 grid (592^3 padded, so 8, FP64), first %d of 1500 time "
+                                             "steps, %.1f s" % (n3, t1 - t0))
+        del vp, sig
+    return out, rec, grf_rec
+
+
+def _vs_fp64(got, want):
+    n = want.shape[0]
+    g = np.asarray(got, dtype=np.float64)[:n]
+    return float(np.linalg.norm(g - want) / np.linalg.norm(want))
 
 
 def bench_gradient(torch, dev, stream):
@@ -248,20 +294,23 @@ def bench_gradient(torch, dev, stream):
 
 def bench_precision(torch, dev, stream, ref_rec):
     """16-bit wavefield storage on layered3d_256: throughput and trace error
-    against the float32 run of the same workload."""
+    against the float32 run of the same workload over all 1000 steps (their
+    error against the FP64 oracle is added from the CPU-baseline sample).
+    Returns (results, traces per storage type)."""
     from paper_1906_10811_amd import Grid
     w, v, wav = make_workload("layered3d_256", torch, dev)
-    res = {}
-    ref = ref_rec.double()
+    res, recs = {}, {}
+    ref = np.asarray(ref_rec, dtype=np.float64)
     for st, scale in (("bf16", 0.0), ("f16", 0.0)):   # f16: automatic power-of-two scale
         g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, amp_scale=scale,
                  stream=stream)
         secs, rec = time_forward(torch, g, w, wav, 1, 1, stream)
-        err = float((rec.double() - ref).norm() / ref.norm())
+        recs[st] = rec.cpu().numpy()
+        err = float(np.linalg.norm(recs[st] - ref) / np.linalg.norm(ref))
         res[st] = dict(gpts=g.padded_points * w["nt"] / secs / 1e9, rel_l2_vs_f32=err,
                        b_alg_per_pt=10, amp_scale=scale)
         g.close()
-    return res
+    return res, recs
 
 
 def bench_adjoint(torch, dev, stream):
@@ -292,24 +341,29 @@ def bench_grf512(torch, dev, stream):
     """The precision workload at full size: grf3d_512 (512^3 + 40 damping =
     592^3 padded, Gaussian random field, so 8, 1500 steps), one forward each
     with FP32, F16 (automatic scale) and BF16 wavefields; 16-bit traces are
-    compared with the FP32 run (their error against the FP64 oracle is
-    measured at a size the oracle can run, in the tests)."""
+    compared with the FP32 run over all 1500 steps, and every storage type
+    with the FP64 oracle over the first 100 steps (the CPU-baseline slice).
+    Returns (results, traces per storage type, (workload, velocity))."""
     from paper_1906_10811_amd import Grid
-    w, v, wav = make_workload("grf3d_512", torch, dev)
-    res, ref = {}, None
+    w = synth.workload("grf3d_512")
+    v_host = synth.velocity(w)
+    v = torch.from_numpy(v_host).to(dev)
+    wav = torch.from_numpy(synth.wavelets(w)).to(dev)
+    res, recs, ref = {}, {}, None
     for st in ("f32", "f16", "bf16"):
         g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, stream=stream)
         secs, rec = time_forward(torch, g, w, wav, 1, 0, stream)
+        recs[st] = rec.cpu().numpy()
         gp = g.padded_points * w["nt"] / secs / 1e9
         b = B_STEP if st == "f32" else 10.0
         res[st] = dict(gpts=round(gp, 1), frac_hbm=round(gp * b / HBM_PEAK_GBS, 4), b_alg_per_pt=b)
         if st == "f32":
-            ref = rec.double()
+            ref = recs[st].astype(np.float64)
         else:
-            res[st]["rel_l2_vs_f32"] = float((rec.double() - ref).norm() / ref.norm())
+            res[st]["rel_l2_vs_f32"] = float(np.linalg.norm(recs[st] - ref) / np.linalg.norm(ref))
         g.close()
     del v
-    return res
+    return res, recs, (w, v_host)
 
 
 def bench_sinc(torch, dev, stream):
@@ -329,10 +383,20 @@ def bench_sinc(torch, dev, stream):
     return res
 
 
-def bench_serving(torch, n=64, budget_gib=8.0, slots=6):
-    """Shot server: n requests with Poisson arrivals at 0.8x the measured
-    one-at-a-time capacity; reports shots/s, p50/p99 latency and the
-    throughput in Gpts/s, against plain one-at-a-time FP32 stepping."""
+def bench_serving(torch, n=64, slots=6, budget_gib=2.0, roomy_gib=32.0):
+    """Shot server on the serving workload (64 requests, grids of 9-38 M
+    padded points, so 4/8/12, 500-1000 steps, FP32).  Poisson arrivals at
+    0.8x the measured one-at-a-time capacity.  Runs, each with shots/s,
+    Gpts/s, p50/p99 latency (submission to completion, numpy linear
+    percentiles) and the peak arena bytes and resident requests:
+      fifo_one_at_a_time  plain FP32 stepping one shot at a time (one slot),
+                          same arrivals: the baseline;
+      batched             continuous batching, `slots` slots, a roomy arena
+                          (the budget does not bind);
+      batched_budget      the same with a budget that binds (2 GiB: about
+                          three of the largest shots at once);
+      saturated_*         all requests at t = 0, one slot and `slots` slots
+                          (throughput without arrival gaps)."""
     from paper_1906_10811_amd import Server
     reqs = synth.serving_requests(n=n, seed=2, rate_hz=1.0)
     shots = []
@@ -341,37 +405,43 @@ def bench_serving(torch, n=64, budget_gib=8.0, slots=6):
         wav = synth.ricker(r["nt"], r["dt"], r["f0"]).astype(np.float32)[:, None]
         shots.append(dict(shape=r["shape"], spacing=r["spacing"], space_order=r["space_order"], nbl=r["nbl"],
                           vp=v, src_xyz=r["src"], wavelet=wav, rec_xyz=r["rec"], dt=r["dt"]))
-    pts = [math.prod(s + 2 * 40 for s in r["shape"]) * r["nt"] for r in reqs]
-    srv = Server(int(budget_gib * 2 ** 30), max_slots=1)
-    t0 = time.perf_counter()
-    for s in shots:
-        srv.wait(srv.submit(**s))
-    serial = time.perf_counter() - t0
-    srv.close()
-    cap = n / serial
-    rate = 0.8 * cap
+    pts = sum(math.prod(s + 2 * 40 for s in r["shape"]) * r["nt"] for r in reqs)
+
+    def run(budget_gib, nslots, arrivals):
+        srv = Server(int(budget_gib * 2 ** 30), max_slots=nslots)
+        t0 = time.perf_counter()
+        tickets = []
+        for a, s in zip(arrivals, shots):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            tickets.append(srv.submit(**s))
+        lat = []
+        for t in tickets:
+            _, info = srv.wait(t)
+            lat.append(info["t_done"] - info["t_submit"])
+        total = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return dict(budget_gib=budget_gib, slots=nslots, shots_per_s=round(n / total, 3),
+                    gpts=round(pts / total / 1e9, 1), p50_s=round(float(np.percentile(lat, 50)), 4),
+                    p99_s=round(float(np.percentile(lat, 99)), 4), makespan_s=round(total, 3),
+                    peak_gb=round(st["peak_bytes"] / 1e9, 3), peak_slots=st["peak_slots"])
+
+    zeros = np.zeros(n)
+    sat1 = run(roomy_gib, 1, zeros)
+    cap = sat1["shots_per_s"]
     rng = np.random.default_rng(7)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
-    srv = Server(int(budget_gib * 2 ** 30), max_slots=slots)
-    t0 = time.perf_counter()
-    tickets = []
-    for a, s in zip(arrivals, shots):
-        now = time.perf_counter() - t0
-        if a > now:
-            time.sleep(a - now)
-        tickets.append((time.perf_counter() - t0, srv.submit(**s)))
-    lat = []
-    for ts, t in tickets:
-        _, info = srv.wait(t)
-        lat.append(info["t_done"] - info["t_submit"])
-    total = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
-    return dict(requests=n, budget_gib=budget_gib, slots=slots, arrival_rate_hz=rate,
-                serial_shots_per_s=cap, serial_gpts=sum(pts) / serial / 1e9,
-                shots_per_s=n / total, gpts=sum(pts) / total / 1e9,
-                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                peak_bytes=st["peak_bytes"], peak_slots=st["peak_slots"])
+    arrivals = np.cumsum(rng.exponential(1.0 / (0.8 * cap), size=n))
+    out = dict(requests=n, arrival_rate_hz=round(0.8 * cap, 3), capacity_one_at_a_time_shots_per_s=cap,
+               request_gb=[round(min(Server.request_bytes(**s) for s in shots) / 1e9, 3),
+                           round(max(Server.request_bytes(**s) for s in shots) / 1e9, 3)])
+    out["fifo_one_at_a_time"] = run(roomy_gib, 1, arrivals)
+    out["batched"] = run(roomy_gib, slots, arrivals)
+    out["batched_budget"] = run(budget_gib, slots, arrivals)
+    out["saturated_one_slot"] = sat1
+    out["saturated_batched"] = run(roomy_gib, slots, zeros)
+    return out
 
 
 def bench_diffusion(torch, dev, stream):
@@ -481,25 +551,32 @@ def main():
                    "space_order": 8, "time_steps_per_bench_step": w["nt"], "sources": 1, "receivers": 256},
         "interior_gpts": round(h["interior"], 3),
         "pct_hbm_roofline": round(100.0 * h["achieved"] / HBM_PEAK_GBS, 2),
-        "stream_copy_gbs": round(copy_gbs, 1),
-        "pct_of_stream_copy": round(100.0 * h["achieved"] / copy_gbs, 2),
+        "blit_copy_gbs": round(copy_gbs, 1),
         "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(h["achieved"] / HBM_PEAK_GBS, 4),
-                     "traffic": h["traffic"], "kernel": "k_step3d<R=4,f32>",
-                     "bytes_per_point": B_STEP, "points_per_launch": h["pts"],
-                     "avg_launch_us": round(h["launch_us"], 2)},
+                     "traffic": h["traffic"],
+                     "kernel": "k_step3d_t2<R=4>" if h["time_block"] == 2 else "k_step3d<R=4,f32>",
+                     "steps_per_launch": h["time_block"], "bytes_per_point_step": h["b_step"],
+                     "bytes_per_launch": h["b_step"] * h["time_block"] * h["pts"],
+                     "points_per_launch": h["pts"], "avg_launch_us": round(h["launch_us"], 2)},
     }
+    # the other launch form on the same workload: two leapfrog levels per
+    # launch (3D temporal blocking, 10 B per point-step) when the headline
+    # runs one step per launch, and the reverse
+    other = 2 if h["time_block"] == 1 else 1
+    _, h2 = bench_headline(torch, dev, max(1, args.steps // 2), 1, stream, time_block=other)
+    line["two_levels_per_launch" if other == 2 else "one_step_per_launch"] = dict(
+        gpts=round(h2["gpts"], 3), ms_per_step=round(h2["ms_per_step"], 3),
+        kernel="k_step3d_t2<R=4>" if other == 2 else "k_step3d<R=4,f32>", zchunk=h2["zchunk"],
+        avg_launch_us=round(h2["launch_us"], 2), bytes_per_point_step=h2["b_step"],
+        frac=round(h2["achieved"] / HBM_PEAK_GBS, 4), traces_equal_bitwise=bool(np.array_equal(h2["rec"], h["rec"])))
+    recs16, grf = {}, None
     if "precision" in extras:
         log("precision: 16-bit storage")
-        from paper_1906_10811_amd import Grid  # noqa: F401
-        w2, v2, wav2 = make_workload("layered3d_256", torch, dev)
-        g = Grid(w2["shape"], w2["spacing"], v2, space_order=8, nbl=w2["nbl"], stream=stream)
-        _, ref = time_forward(torch, g, w2, wav2, 1, 0, stream)
-        g.close()
-        line["precision"] = bench_precision(torch, dev, stream, ref)
+        line["precision"], recs16 = bench_precision(torch, dev, stream, h["rec"])
     if "grf512" in extras:
         log("precision workload at full size: grf3d_512")
-        line["grf512"] = bench_grf512(torch, dev, stream)
+        line["grf512"], grf_recs, grf = bench_grf512(torch, dev, stream)
     if "adjoint" in extras:
         log("adjoint: layered3d_256")
         line["adjoint"] = bench_adjoint(torch, dev, stream)
@@ -517,7 +594,15 @@ def main():
         line["serving"] = bench_serving(torch)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = bench_cpu_baseline(w)
+        cpu, ref64, grf64 = bench_cpu_baseline(w, grf)
+        line["cpu_baseline"] = cpu
+        # the GPU traces of the sampled steps against the FP64 oracle's
+        n = ref64.shape[0]
+        line["vs_fp64_first_%d_steps" % n] = dict(
+            f32=_vs_fp64(h["rec"], ref64), **{st: _vs_fp64(r, ref64) for st, r in recs16.items()})
+        if grf64 is not None:
+            line["grf512"]["vs_fp64_first_%d_steps" % grf64.shape[0]] = {
+                st: _vs_fp64(r, grf64) for st, r in grf_recs.items()}
     print(json.dumps(line), flush=True)
 
 

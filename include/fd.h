@@ -104,6 +104,13 @@ typedef struct fd_grid_desc {
                               points; 64 x 16 alone when there is none; space orders 14
                               and 16 run 32 x 32 instead), 0 selects automatically; any
                               other value is FD_ERR_ARG; ignored in 2D */
+    int time_block;        /* time steps per launch of fd_forward and the server: 1 one
+                              step per launch; 2 two leapfrog levels per launch (3D,
+                              float32 storage, space order <= 8 only: 64 x 16 tiles
+                              whatever tile_x says, two more wavefield buffers in the
+                              workspace); 0 selects automatically (one step: faster on
+                              every grid measured); anything else, or 2 where it is not
+                              available, is FD_ERR_ARG */
 } fd_grid_desc;
 
 /* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
@@ -137,6 +144,7 @@ typedef struct fd_grid_info {
     int tile_strip;        /* 3D: width of the last x column when it runs 32 x 32 tiles
                               beside 64 x 16 ones, else 0 */
     int zchunk;            /* 3D: z planes per workgroup of a plain step; 2D: 64 */
+    int time_block;        /* steps per launch of fd_forward (1 or 2) */
 } fd_grid_info;
 
 typedef struct fd_grid fd_grid;

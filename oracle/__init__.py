@@ -89,6 +89,8 @@ def _load():
         lib.orc_imaging.restype = None
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -96,6 +98,11 @@ def _load():
 def num_threads() -> int:
     """OpenMP threads the oracle's loops run on."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Run the oracle's loops on n threads from now on."""
+    _load().orc_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

@@ -227,6 +227,18 @@ void orc_imaging(int ndim, const long *n, const double *sigma, double dt, int nt
     }
 }
 
+/* Threads for the loops above from now on (n >= 1; the CPU baseline times
+   the oracle on one core as well as on all of them). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* OpenMP thread count actually used by the loops above (for reporting). */
 int orc_num_threads(void)
 {

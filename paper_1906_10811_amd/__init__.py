@@ -55,7 +55,8 @@ class Grid:
     def __init__(self, shape, spacing, vp: torch.Tensor, space_order: int = 8, nbl: int = 0,
                  origin=None, damp_max: float = 0.0, storage: str = "f32", amp_scale: float = 0.0,
                  vp_padded: bool = False, max_src: int = 0, max_rec: int = 0, zchunk: int = 0,
-                 sinc_radius: int = 0, sinc_beta: float = 0.0, tile_x: int = 0, stream=None):
+                 sinc_radius: int = 0, sinc_beta: float = 0.0, tile_x: int = 0, time_block: int = 0,
+                 stream=None):
         lib = _lib.load()
         ndim = len(shape)
         self.ndim = ndim
@@ -77,6 +78,7 @@ class Grid:
         d.sinc_radius = int(sinc_radius)
         d.sinc_beta = float(sinc_beta)
         d.tile_x = int(tile_x)
+        d.time_block = int(time_block)
         self.desc = d
         nbytes = ctypes.c_size_t()
         _lib.check(lib.fd_grid_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
@@ -102,6 +104,7 @@ class Grid:
         self.tile = (int(info.tile[0]), int(info.tile[1]))
         self.tile_strip = int(info.tile_strip)
         self.zchunk = int(info.zchunk)
+        self.time_block = int(info.time_block)
 
     @property
     def array_shape(self):
@@ -299,7 +302,7 @@ class Server:
 
     @staticmethod
     def _request(shape, spacing, space_order, nbl, vp, src_xyz, wavelet, rec_xyz, dt, storage="f32",
-                 origin=None, amp_scale=0.0, sinc_radius=0, sinc_beta=0.0):
+                 origin=None, amp_scale=0.0, sinc_radius=0, sinc_beta=0.0, time_block=0):
         ndim = len(shape)
         r = _lib.Request()
         g = r.grid
@@ -314,6 +317,7 @@ class Server:
         g.amp_scale = float(amp_scale)
         g.sinc_radius = int(sinc_radius)
         g.sinc_beta = float(sinc_beta)
+        g.time_block = int(time_block)
         vp = np.ascontiguousarray(vp, dtype=np.float32)
         src = _coords(src_xyz, ndim)
         rec = _coords(rec_xyz, ndim)

@@ -56,6 +56,7 @@ class GridDesc(ctypes.Structure):
         ("sinc_radius", ctypes.c_int),
         ("sinc_beta", ctypes.c_double),
         ("tile_x", ctypes.c_int),
+        ("time_block", ctypes.c_int),
     ]
 
 
@@ -90,6 +91,7 @@ class GridInfo(ctypes.Structure):
         ("tile", ctypes.c_int * 2),
         ("tile_strip", ctypes.c_int),
         ("zchunk", ctypes.c_int),
+        ("time_block", ctypes.c_int),
     ]
 
 

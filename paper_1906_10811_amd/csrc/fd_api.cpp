@@ -114,6 +114,10 @@ bool fdi_check_desc(const fd_grid_desc *d) {
     if (d->sinc_radius < 0 || d->sinc_radius > kMaxSincR)
         return fdi_fail(FD_ERR_ARG, "sinc_radius must be 0..%d", kMaxSincR), false;
     if (!std::isfinite(d->sinc_beta)) return fdi_fail(FD_ERR_ARG, "sinc_beta"), false;
+    if (d->time_block < 0 || d->time_block > 2) return fdi_fail(FD_ERR_ARG, "time_block must be 0, 1 or 2"), false;
+    if (d->time_block == 2 && !(d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR))
+        return fdi_fail(FD_ERR_ARG, "time_block 2 needs a 3D float32 grid of space order <= %d", 2 * kT2MaxR),
+               false;
     long long pts = 1;
     for (int a = 0; a < d->ndim; ++a) pts *= (long long)d->shape[a] + 2LL * d->nbl;
     if (pts > (1LL << 34)) return fdi_fail(FD_ERR_ARG, "grid too large"), false;
@@ -157,7 +161,9 @@ struct SparseDev {   // device tables of one side (sources or receivers)
 };
 
 struct WsPlan {
-    size_t vel, p, uA, uB, damp, misc, total;
+    size_t vel, p, uA, uB, uC, uD, damp, misc, total;
+    size_t t2pp, t2corner;   // extended source tables of the two-level step (0 when unused)
+    size_t stage_t2;         // their host staging area
     size_t src[6], rec[6];   // idx, w, plane_ptr, corner, ent_src, ent_w
     size_t field_bytes;
     int cap_src, cap_rec;
@@ -203,6 +209,19 @@ int sparse_nodes(const fd_grid_desc *d) {
 constexpr double kTileNarrowGain = 0.06;   // lane-use margin that selects 32 x 32 at so 10, 12
 
 bool mixed_fits(const Layout &L) { return L.nx > 64 && L.nx % 64 != 0 && L.nx % 64 <= 32; }
+
+// Whether fd_forward runs two leapfrog levels per launch (k_step3d_t2):
+// only on request.  Measured on layered3d_256 (336^3, so 8): 312 Gpts/s
+// against 370 for one step per launch (it reads 1.41x its algorithmic
+// bytes, and with 256 registers per lane it keeps only one plane of loads
+// in flight), so the automatic choice is one step per launch.
+bool t2_enabled(const fd_grid_desc *d) {
+    return d->time_block == 2 && d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR;
+}
+
+// Tiles of the two-level step: 64 x 16 whatever the one-step shape.
+inline int t2_ntx(const Layout &L) { return (L.nx + 63) / 64; }
+inline int t2_nty(const Layout &L) { return (L.ny + 15) / 16; }
 
 // Tile shape code of a grid (16, 8 or kShapeMixed; 2D grids: 16).
 int tile_shape(const fd_grid_desc *d, const Layout &L) {
@@ -256,10 +275,19 @@ WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     w.p = o; o += f32;
     w.uA = o; o += w.field_bytes;
     w.uB = o; o += w.field_bytes;
+    const bool t2 = t2_enabled(d);
+    w.uC = o; if (t2) o += w.field_bytes;
+    w.uD = o; if (t2) o += w.field_bytes;
     w.damp = o; o = align_up(o + sizeof(float) * (size_t)(L.nx + L.ny + L.nz), 256);
     w.misc = o; o = align_up(o + sizeof(double) * kNPart + 256, 256);
     o += side_bytes(w.cap_src, nc, nptr, w.src, o);
     o += side_bytes(w.cap_rec, nc, nptr, w.rec, o);
+    // two-level step: per 64 x 16 tile, the source grid points of the tile
+    // grown by its ring (a point lies in at most 4 grown tiles)
+    const size_t t2ptr = t2 ? (size_t)t2_ntx(L) * t2_nty(L) * (L.nz + 1) : 0;
+    const size_t t2cor = t2 ? (size_t)4 * w.cap_src * nc : 0;
+    w.t2pp = o; o = align_up(o + sizeof(int) * t2ptr, 256);
+    w.t2corner = o; o = align_up(o + sizeof(int4) * t2cor, 256);
     w.total = o;
     // host staging mirrors the uploaded regions
     size_t s = 0;
@@ -270,6 +298,8 @@ WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     w.stage_rec = s;
     w.stage_side_bytes_rec = w.rec[5] + align_up(sizeof(float) * (size_t)w.cap_rec * nc, 256) - w.rec[0];
     s += w.stage_side_bytes_rec;
+    w.stage_t2 = s;
+    s += w.total - w.t2pp;
     w.stage_bytes = s;
     return w;
 }
@@ -308,6 +338,17 @@ struct fd_grid {
     hipStream_t last_stream;   // stream of the latest enqueued work
     bool has_last_stream;
     bool auto_amp;             // F16 storage with the scale chosen per dt
+    // forward state: u^n in cur, u^{n-1} in prev (two of uA..uD); rows of
+    // the traces sampled so far in the current run
+    void *cur, *prev;
+    int rows_done;
+    // two-level step
+    bool t2;
+    void *uC, *uD;
+    int t2_ntz, t2_zchunk;
+    int *t2_pp;
+    int4 *t2_corner;
+    int t2_ncorner;
 };
 
 namespace {
@@ -542,6 +583,45 @@ int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s
                             sizeof(int4) * corners.size(), sizeof(int) * esrc.size(), sizeof(float) * ew.size()};
     for (int k = 0; k < 6; ++k)
         if (used[k]) HIPCHK(hipMemcpyAsync(g->ws + off[k], st + (off[k] - base), used[k], hipMemcpyHostToDevice, s));
+    if (side == 0 && g->t2) {
+        // Extended tables of the two-level step: for each 64 x 16 tile, the
+        // source grid points inside the tile grown by the ring its level-1
+        // region covers (R rows in y, R rounded up to whole float4 groups in
+        // x), per plane, in (tile, z, y, x) order; the entries are those of
+        // the point's corner above.
+        const int r = L.r, hx = 4 * ((r + 3) / 4);
+        const int ntx2 = t2_ntx(L), nty2 = t2_nty(L);
+        struct Ext { int tile, z, y, x, corner; };
+        std::vector<Ext> ext;
+        ext.reserve(corners.size() * 4);
+        for (size_t c = 0; c < corners.size(); ++c) {
+            const int x = corners[c].x, y = corners[c].y;
+            const int z = (int)(ckey[c] % (L.nz + 1));
+            for (int ty = std::max(0, y / 16 - 1); ty <= std::min(nty2 - 1, y / 16 + 1); ++ty)
+                for (int tx = std::max(0, x / 64 - 1); tx <= std::min(ntx2 - 1, x / 64 + 1); ++tx)
+                    if (x >= 64 * tx - hx && x < 64 * tx + 64 + hx && y >= 16 * ty - r && y < 16 * ty + 16 + r)
+                        ext.push_back({ty * ntx2 + tx, z, y, x, (int)c});
+        }
+        std::sort(ext.begin(), ext.end(), [](const Ext &a, const Ext &b) {
+            if (a.tile != b.tile) return a.tile < b.tile;
+            if (a.z != b.z) return a.z < b.z;
+            if (a.y != b.y) return a.y < b.y;
+            return a.x < b.x;
+        });
+        const size_t nptr2 = (size_t)ntx2 * nty2 * (L.nz + 1);
+        int *pp2 = (int *)(g->stage + g->wp.stage_t2);
+        int4 *cor2 = (int4 *)(g->stage + g->wp.stage_t2 + (g->wp.t2corner - g->wp.t2pp));
+        size_t e = 0;
+        for (size_t k = 0; k < nptr2; ++k) {
+            while (e < ext.size() && (long long)ext[e].tile * (L.nz + 1) + ext[e].z < (long long)k) ++e;
+            pp2[k] = (int)e;
+        }
+        for (size_t i = 0; i < ext.size(); ++i) cor2[i] = corners[ext[i].corner];
+        HIPCHK(hipMemcpyAsync(g->t2_pp, pp2, sizeof(int) * nptr2, hipMemcpyHostToDevice, s));
+        if (!ext.empty())
+            HIPCHK(hipMemcpyAsync(g->t2_corner, cor2, sizeof(int4) * ext.size(), hipMemcpyHostToDevice, s));
+        g->t2_ncorner = (int)ext.size();
+    }
     rc = stage_release(g, s);
     if (rc) return rc;
     g->cached_xyz[side] = std::move(key);
@@ -679,6 +759,15 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     g->p = (float *)(g->ws + wp.p);
     g->uA = g->ws + wp.uA;
     g->uB = g->ws + wp.uB;
+    g->t2 = t2_enabled(desc);
+    g->uC = g->ws + wp.uC;
+    g->uD = g->ws + wp.uD;
+    g->t2_pp = (int *)(g->ws + wp.t2pp);
+    g->t2_corner = (int4 *)(g->ws + wp.t2corner);
+    g->t2_ncorner = 0;
+    g->cur = g->uA;
+    g->prev = g->uB;
+    g->rows_done = 0;
     g->damp = (float *)(g->ws + wp.damp);
     g->partials = (double *)(g->ws + wp.misc);
     g->vmax_bits = (unsigned *)(g->ws + wp.misc + sizeof(double) * kNPart);
@@ -766,11 +855,32 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
         g->zchunk[m] = std::min(std::min(zc, L.nz), kMaxChunk);
         g->ntz[m] = (L.nz + g->zchunk[m] - 1) / g->zchunk[m];
     }
+    if (g->t2) {
+        // two-level step: one balanced round of workgroups as above, at the
+        // kernel's own occupancy; each z chunk recomputes R level-1 planes at
+        // either end (shared with the neighbouring chunks), so chunks stay
+        // long
+        int zc = desc->zchunk;
+        if (zc <= 0) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
+                cus <= 0)
+                cus = 256;
+            const int occ = std::max(1, step_t2_blocks_per_cu(L.r));
+            const int tiles = t2_ntx(L) * t2_nty(L);
+            const int nzc = std::max(1, std::min(L.nz, occ * cus / tiles));
+            zc = (L.nz + nzc - 1) / nzc;
+        }
+        g->t2_zchunk = std::min(std::min(zc, L.nz), kMaxChunk);
+        g->t2_ntz = (L.nz + g->t2_zchunk - 1) / g->t2_zchunk;
+    }
 
     // zero every field (halos included), fill velocity, find v_max
     hipError_t e = hipSuccess;
     if ((e = launch_zero_field(L, g->uA, g->st, s)) != hipSuccess ||
         (e = launch_zero_field(L, g->uB, g->st, s)) != hipSuccess ||
+        (g->t2 && (e = launch_zero_field(L, g->uC, g->st, s)) != hipSuccess) ||
+        (g->t2 && (e = launch_zero_field(L, g->uD, g->st, s)) != hipSuccess) ||
         (e = launch_zero_field(L, g->vel, Store::F32, s)) != hipSuccess ||
         (e = launch_zero_field(L, g->p, Store::F32, s)) != hipSuccess)
         return cleanup(fdi_fail(FD_ERR_DEVICE, "zero fill: %s", hipGetErrorString(e)));
@@ -842,41 +952,93 @@ extern "C" int fd_grid_get_info(const fd_grid *g, fd_grid_info *info) {
     info->tile[1] = g->d.ndim == 3 ? tile3_y(tw4) : kTile2Z;
     info->tile_strip = g->nstrip > 0 ? g->L.nx - 64 * g->ntx : 0;
     info->zchunk = g->zchunk[kPlain];
+    info->time_block = g->t2 ? 2 : 1;
     return FD_OK;
 }
 
-// Enqueue forward steps n0 .. n1-1 of an nt-step run whose initial state
-// (u^0, u^{-1}) was placed in (uA, uB).  The in-place rotation puts u^n in uA
-// for even n and in uB for odd n, so a run can be advanced in chunks.
-// Receiver row n-1 is sampled inside step n; row nt-1 after the last step.
-// If ckpt is given, (u^c, u^{c-1}) is copied to ckpt[2*(c/K)], ckpt[2*(c/K)+1]
-// before step c for every multiple c of K.
+// Enqueue forward steps n0 .. n1-1 of an nt-step run continuing from the
+// grid's state (u^n0 in g->cur, u^{n0-1} in g->prev; a run can be advanced
+// in chunks).  Trace row n-1 samples u^n: the one-step kernel samples its
+// centre field in the launch that starts from it; the two-level kernel
+// samples both its input levels (rows n-1 and n-2) in the launch that starts
+// from level n.  g->rows_done counts the rows sampled so far; before a
+// one-step launch overwrites u^{n-1} in place, a row left to it is sampled
+// first, and the last chunk samples what remains.  If ckpt is given, (u^c,
+// u^{c-1}) is copied to ckpt[2*(c/K)], ckpt[2*(c/K)+1] before step c for
+// every multiple c of K (one step per launch then).
 int fdi_forward_steps(fd_grid *g, const fd_shot *sh, int nt, int n0, int n1, float *rec_out,
                       void **ckpt, int K, hipStream_t s) {
     note_stream(g, s);
     StepArgs a = base_args(g);
-    void *A = (n0 % 2 == 0) ? g->uA : g->uB;
-    void *B = (n0 % 2 == 0) ? g->uB : g->uA;
     const float inj_scale = (float)(g->amp / g->cell);
     const float smp_scale = 1.f / g->amp;
-    for (int n = n0; n < n1; ++n) {
-        if (ckpt && n % K == 0) {
-            HIPCHK(hipMemcpyAsync(ckpt[2 * (n / K)], A, g->wp.field_bytes, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(ckpt[2 * (n / K) + 1], B, g->wp.field_bytes, hipMemcpyDeviceToDevice, s));
+    auto row = [&](int r) -> float * {
+        return (rec_out && r >= 0 && r < nt && r >= g->rows_done) ? rec_out + (size_t)r * sh->nrec : nullptr;
+    };
+    const bool t2 = g->t2 && !ckpt;
+    int n = n0;
+    while (n < n1) {
+        if (t2 && n + 2 <= n1) {
+            // two levels: u^{n+1} and u^{n+2} into the pair not holding u^n, u^{n-1}
+            void *fa = nullptr, *fb = nullptr;
+            void *bufs[4] = {g->uA, g->uB, g->uC, g->uD};
+            for (void *b : bufs)
+                if (b != g->cur && b != g->prev) (fa ? fb : fa) = b;
+            StepArgs t = a;
+            t.u = g->cur;
+            t.prev = g->prev;
+            t.out = fb;    // u^{n+1}
+            t.out2 = fa;   // u^{n+2}
+            t.ntx = t2_ntx(g->L);
+            t.nty = t2_nty(g->L);
+            t.ntz = g->t2_ntz;
+            t.zchunk = g->t2_zchunk;
+            const SparseDev &d = g->sd[0];
+            const bool any = g->ncorner[0] > 0;
+            t.inj = Inject{g->t2_pp, g->t2_corner, d.ent_src, d.ent_w,
+                           any ? sh->src_wavelet + (size_t)n * sh->nsrc : nullptr, inj_scale};
+            t.inj2 = Inject{g->t2_pp, g->t2_corner, d.ent_src, d.ent_w,
+                            any ? sh->src_wavelet + (size_t)(n + 1) * sh->nsrc : nullptr, inj_scale};
+            t.smp = make_sample(g, 1, sh->nrec, row(n - 1), smp_scale);
+            t.nsamp_blocks = samp_blocks(t.smp);
+            t.smp2 = make_sample(g, 1, sh->nrec, row(n - 2), smp_scale);
+            t.nsamp_blocks2 = samp_blocks(t.smp2);
+            HIPCHK(launch_step_t2(t, s));
+            g->rows_done = std::max(g->rows_done, std::min(n, nt));
+            g->prev = fb;
+            g->cur = fa;
+            n += 2;
+            continue;
         }
-        a.u = A;
-        a.prev = B;
-        a.out = B;
+        if (ckpt && n % K == 0) {
+            HIPCHK(hipMemcpyAsync(ckpt[2 * (n / K)], g->cur, g->wp.field_bytes, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(ckpt[2 * (n / K) + 1], g->prev, g->wp.field_bytes, hipMemcpyDeviceToDevice, s));
+        }
+        if (float *r2 = row(n - 2)) {   // u^{n-1} is about to be overwritten
+            Sample sm = make_sample(g, 1, sh->nrec, r2, smp_scale);
+            HIPCHK(launch_sample(sm, g->prev, g->st, s));
+        }
+        a.u = g->cur;
+        a.prev = g->prev;
+        a.out = g->prev;
         a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, inj_scale);
-        a.smp = make_sample(g, 1, sh->nrec, (rec_out && n >= 1) ? rec_out + (size_t)(n - 1) * sh->nrec : nullptr,
-                            smp_scale);
+        a.smp = make_sample(g, 1, sh->nrec, row(n - 1), smp_scale);
         a.nsamp_blocks = samp_blocks(a.smp);
         HIPCHK(launch_step(a, g->st, kPlain, s));
-        std::swap(A, B);
+        g->rows_done = std::max(g->rows_done, std::min(n, nt));
+        std::swap(g->cur, g->prev);
+        ++n;
     }
-    if (rec_out && n1 == nt && nt >= 1) {
-        Sample sm = make_sample(g, 1, sh->nrec, rec_out + (size_t)(nt - 1) * sh->nrec, smp_scale);
-        HIPCHK(launch_sample(sm, A, g->st, s));
+    if (n1 == nt && nt >= 1) {
+        if (float *r2 = row(nt - 2)) {
+            Sample sm = make_sample(g, 1, sh->nrec, r2, smp_scale);
+            HIPCHK(launch_sample(sm, g->prev, g->st, s));
+        }
+        if (float *r1 = row(nt - 1)) {
+            Sample sm = make_sample(g, 1, sh->nrec, r1, smp_scale);
+            HIPCHK(launch_sample(sm, g->cur, g->st, s));
+        }
+        g->rows_done = nt;
     }
     return FD_OK;
 }
@@ -894,10 +1056,13 @@ int fdi_forward_prepare(fd_grid *g, const fd_shot *sh, int nt, double dt, hipStr
     return FD_OK;
 }
 
-// Zero initial state (u^0 = u^{-1} = 0).
+// Zero initial state (u^0 = u^{-1} = 0) in uA, uB, and a new run's rows.
 int fdi_forward_zero_state(fd_grid *g, hipStream_t s) {
     HIPCHK(launch_zero_field(g->L, g->uA, g->st, s));
     HIPCHK(launch_zero_field(g->L, g->uB, g->st, s));
+    g->cur = g->uA;
+    g->prev = g->uB;
+    g->rows_done = 0;
     return FD_OK;
 }
 
@@ -917,11 +1082,13 @@ extern "C" int fd_forward(fd_grid *g, const fd_shot *sh, int nt, double dt, floa
     else HIPCHK(launch_zero_field(L, g->uA, g->st, s));
     if (opts && opts->u_prev) HIPCHK(launch_dense_to_field(L, opts->u_prev, g->uB, g->st, g->amp, s));
     else HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+    g->cur = g->uA;
+    g->prev = g->uB;
+    g->rows_done = 0;
     if ((rc = fdi_forward_steps(g, sh, nt, 0, nt, rec_out, nullptr, 1, s))) return rc;
-    void *cur = (nt % 2 == 0) ? g->uA : g->uB;
-    void *prv = (nt % 2 == 0) ? g->uB : g->uA;
-    if (opts && opts->save_u) HIPCHK(launch_field_to_dense(L, cur, opts->save_u, g->st, 1.f / g->amp, s));
-    if (opts && opts->save_u_prev) HIPCHK(launch_field_to_dense(L, prv, opts->save_u_prev, g->st, 1.f / g->amp, s));
+    if (opts && opts->save_u) HIPCHK(launch_field_to_dense(L, g->cur, opts->save_u, g->st, 1.f / g->amp, s));
+    if (opts && opts->save_u_prev)
+        HIPCHK(launch_field_to_dense(L, g->prev, opts->save_u_prev, g->st, 1.f / g->amp, s));
     return FD_OK;
     API_GUARD_END
 }
@@ -1132,12 +1299,10 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
         //    go: the sweep below would otherwise recompute exactly these
         //    steps first (the bracket mode's u is bitwise the plain mode's).
         const int clast = (gp.nseg - 1) * K;
-        HIPCHK(launch_zero_field(L, g->uA, g->st, s));
-        HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+        if ((rc = fdi_forward_zero_state(g, s))) return rc;
         if ((rc = fdi_forward_steps(g, sh, nt, 0, clast, recb, ck.data(), K, s))) return rc;
         {
-            void *A = (clast % 2 == 0) ? g->uA : g->uB;   // u^n, u^{n-1}, as the chunked forward leaves them
-            void *B = (clast % 2 == 0) ? g->uB : g->uA;
+            void *A = g->cur, *B = g->prev;   // u^n, u^{n-1}, as the chunked forward leaves them
             for (int n = clast; n < nt; ++n) {
                 if ((rc = bracket_step(n, A, B, B, br[n - clast], recb + (size_t)(n - 1) * sh->nrec))) return rc;
                 std::swap(A, B);

@@ -125,6 +125,14 @@ struct StepArgs {
     Inject inj;
     Sample smp;
     Imaging img;
+    // two-level step (k_step3d_t2): u^{n+2} goes to out2 (out receives
+    // u^{n+1}); inj2 holds the second level's source row (both levels read
+    // the extended tables of inj); smp2 samples the previous field in
+    // nsamp_blocks2 workgroups after the nsamp_blocks that sample u
+    void *out2;
+    Inject inj2;
+    Sample smp2;
+    int nsamp_blocks2;
 };
 
 enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
@@ -134,6 +142,13 @@ int step_blocks_per_cu(int ndim, int r, Store st, int mode, int shape3);
 
 // Launchers (fd_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s);
+// Two leapfrog levels in one launch (3D, float32, radius <= kT2MaxR): 64 x
+// 16 tiles (a.ntx, a.nty), a.ntz z chunks of a.zchunk planes; a.inj points
+// at the extended per-tile source tables (the grid points within the tile
+// grown by R in y and by R rounded up to 4 in x).
+constexpr int kT2MaxR = 4;
+hipError_t launch_step_t2(const StepArgs &a, hipStream_t s);
+int step_t2_blocks_per_cu(int r);
 hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s);
 hipError_t launch_fill_velocity(const Layout &L, const float *vp, int vp_padded, int nbl,
                                 const int *phys, float *vel, hipStream_t s);

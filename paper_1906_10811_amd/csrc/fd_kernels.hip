@@ -602,6 +602,376 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     }
 }
 
+// ------------------------------------------------------ 3D two-level step
+// Temporal blocking of the 2.5D march (the wave-front tiling of Section
+// 2.3.1 and the tiling of Section 2.2, done in registers and LDS): from u^n
+// and u^{n-1} a workgroup computes level 1, u^{n+1}, on its 64 x 16 tile
+// grown by a ring of R points (the ring belongs to the neighbour tiles and
+// is recomputed here, so that no workgroup waits for another), and level 2,
+// u^{n+2}, on its tile, R planes behind level 1 in the z march.  It writes
+// u^{n+1} and u^{n+2} of its tile: per point and two steps HBM carries u^n,
+// u^{n-1} and p in and two fields out, 10 bytes per point-step instead of
+// 16.  The outputs go to a second pair of fields (u^n and u^{n-1} are read
+// as the neighbours' ring until the launch ends).  Each level is the same
+// sequence of float32 operations as the one-step kernel's, so two levels
+// here give bitwise the fields of two one-step launches.
+template <int R>
+struct T2Shape {
+    static constexpr int TW = 16, TY = 16;                   // tile: 16 float4 columns x 16 rows
+    static constexpr int HX4 = (R + 3) / 4;                  // float4 columns of an R-point ring in x
+    static constexpr int W1 = TW + 2 * HX4, H1 = TY + 2 * R;    // level-1 region E1 (float4 x rows)
+    static constexpr int W2 = W1 + 2 * HX4, H2 = H1 + 2 * R;    // staged u^n plane E2
+    static constexpr int N1 = W1 * H1, N2 = W2 * H2;
+    static constexpr int NR1 = N1 - TW * TY;                 // ring groups of E1
+    static constexpr int NR1L = TY * 2 * HX4;                // ... of which in the tile's rows
+    static constexpr int NS = 1 + (NR1 + kBlock - 1) / kBlock;  // level-1 groups per lane (0: own)
+    static constexpr int NR2 = N2 - N1;                      // ring groups of E2 (u^n only)
+    static constexpr int NR2L = H1 * 2 * HX4;
+    static constexpr int HP2 = (NR2 + kBlock - 1) / kBlock;
+    static constexpr int NQ = 2 * R + 1;
+    static constexpr int kMaxPl = kMaxChunk + 2 * R;         // level-1 planes of a chunk
+    // LDS, in float4 (at radius 4 just under the 80 KB that lets two
+    // workgroups share a CU); the level-1 source terms of a plane are
+    // scattered into the staging buffer the next plane will use, idle then
+    static constexpr int kU = 0;                             // [2][N2] staged u^n planes
+    static constexpr int kV = kU + 2 * N2;                   // [R + 1][N1] ring of u^{n+1} planes
+    static constexpr int kP = kV + (R + 1) * N1;             // [R + 1][NR2] parked E2 ring of u^n
+    static constexpr int kS2 = kP + (R + 1) * NR2;           // [kBlock] level-2 source terms
+    static constexpr int kDz = kS2 + kBlock;                 // float [kMaxPl] z damping of level-1 planes
+    static constexpr int kPp = kDz + kMaxPl / 4;             // int [kMaxPl + 1] source plane pointers
+    static constexpr int kSize = kPp + (kMaxPl + 1 + 3) / 4;
+};
+
+// Ring group h of a region W x H (float4 x rows) around an inner block of
+// IW x IH starting at (HX, RY): the RY rows above (full width), then HX
+// columns left and right of each inner row, then the RY rows below.
+template <int W, int H, int IW, int IH, int HX, int RY>
+__device__ inline void ring_pos(int h, int &cx, int &cy) {
+    if (h < RY * W) {
+        cy = h / W;
+        cx = h - cy * W;
+    } else if (h < RY * W + IH * 2 * HX) {
+        const int j = h - RY * W;
+        const int row = j / (2 * HX), c = j - row * (2 * HX);
+        cy = RY + row;
+        cx = c < HX ? c : IW + c;
+    } else {
+        const int j = h - RY * W - IH * 2 * HX;
+        cy = RY + IH + j / W;
+        cx = j - (j / W) * W;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_step3d_t2(const StepArgs a) {
+    using K = T2Shape<R>;
+    constexpr int TW = K::TW, TY = K::TY, HX4 = K::HX4, W1 = K::W1, W2 = K::W2, N1 = K::N1, N2 = K::N2;
+    constexpr int NS = K::NS, HP2 = K::HP2, NQ = K::NQ;
+    __shared__ float4 smem[K::kSize];
+    const int ntile = (int)gridDim.x - a.nsamp_blocks - a.nsamp_blocks2;
+    if ((int)blockIdx.x >= ntile) {
+        const int b = (int)blockIdx.x - ntile;
+        if (b < a.nsamp_blocks)
+            sample_block<Store::F32>(a.smp, a.u, b);
+        else
+            sample_block<Store::F32>(a.smp2, a.prev, b - a.nsamp_blocks);
+        return;
+    }
+    const int t = xcd_remap((int)blockIdx.x, ntile);
+    const int tiles = a.ntx * a.nty;
+    const int tid = t % tiles, bz = t / tiles;
+    const int x0 = (tid % a.ntx) * 4 * TW, y0 = (tid / a.ntx) * TY;
+    const Layout L = a.L;
+    const int c0 = bz * a.zchunk, c1 = min(c0 + a.zchunk, L.nz);
+    const int zl0 = c0 - R;                  // level-1 plane of the first iteration
+    const int npl = c1 - c0 + 2 * R;         // iterations: level-1 planes [c0 - R, c1 + R)
+    const int lane = (int)threadIdx.x;
+    const long long plane = L.plane;
+    const long long zcol = L.offset((L.nx + 3) & ~3, 0, 0);   // zero in every row of every plane
+    const float *__restrict__ U = (const float *)a.u;
+    const float *Pv = (const float *)a.prev;
+    const float *__restrict__ Pp = a.p;
+    float *O1 = (float *)a.out;
+    float *O2 = (float *)a.out2;
+
+    float4 *stg = smem + K::kU;
+    float4 *ring = smem + K::kV;
+    float4 *park = smem + K::kP;
+    float4 *s_src2 = smem + K::kS2;
+    float *s_dz = reinterpret_cast<float *>(smem + K::kDz);
+    int *s_pp = reinterpret_cast<int *>(smem + K::kPp);
+    // per-plane tables of the chunk's level-1 planes (z damping; source plane
+    // pointers, which give no sources outside the grid)
+    const int *tile_pp = a.inj.plane_ptr + (long long)tid * (L.nz + 1);
+    for (int i = lane; i <= npl; i += kBlock) {
+        const int z = zl0 + i;
+        if (i < npl) s_dz[i] = (z >= 0 && z < L.nz) ? a.damp[L.nx + L.ny + z] : 0.f;
+        s_pp[i] = a.inj.vals ? tile_pp[min(max(z, 0), L.nz)] : 0;
+    }
+    s_src2[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    // level-1 groups of this lane: slot 0 its own tile group, slots 1.. ring
+    // groups of E1; grid coordinates, E1 and E2 indices, validity
+    const int tx = lane % TW, ty = lane / TW;
+    int e1i[NS], e2i[NS], gxs[NS];
+    bool in1[NS];
+    long long off[NS];
+    float sxy[NS][4];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        int cx = HX4 + tx, cy = R + ty;
+        bool used = true;
+        if (k > 0) {
+            const int h = lane + (k - 1) * kBlock;
+            used = h < K::NR1;
+            ring_pos<W1, K::H1, TW, TY, HX4, R>(used ? h : 0, cx, cy);
+        }
+        const int gx = x0 - 4 * HX4 + 4 * cx, gy = y0 - R + cy;
+        in1[k] = used && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny;
+        e1i[k] = used ? cy * W1 + cx : -1;
+        e2i[k] = (cy + R) * W2 + cx + HX4;
+        gxs[k] = gx;
+        off[k] = in1[k] ? L.offset(gx, gy, 0) : zcol;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            sxy[k][i] = in1[k] ? a.damp[min(gx + i, L.nx - 1)] + a.damp[L.nx + gy] : 0.f;
+    }
+    // the E2 ring of u^n (staged for level 1's x and y neighbours only)
+    int h2i[HP2];
+    long long hoff[HP2];
+#pragma unroll
+    for (int k = 0; k < HP2; ++k) {
+        const int h = lane + k * kBlock;
+        int cx = 0, cy = 0;
+        ring_pos<W2, K::H2, W1, K::H1, HX4, R>(h < K::NR2 ? h : 0, cx, cy);
+        const int gx = x0 - 8 * HX4 + 4 * cx, gy = y0 - 2 * R + cy;
+        const bool ok = h < K::NR2 && gx >= 0 && gx < L.nx && gy >= 0 && gy < L.ny;
+        h2i[k] = h < K::NR2 ? cy * W2 + cx : -1;
+        hoff[k] = ok ? L.offset(gx, gy, 0) : zcol;
+    }
+    const bool act = in1[0];                      // the lane's tile group is inside the grid
+    const int nvalid = L.nx - gxs[0];
+
+    auto zclamp = [&](int z) { return min(max(z, -R), L.nz + R - 1); };
+    // z queues: q[k][j] = u^n of slot k at plane zl - R + j; w[j] = u^{n+1}
+    // of slot 0 at plane zl - 2R + j; pq[j] = p of slot 0 at plane zl - R + j
+    float4 q[NS][NQ], w[NQ], pq[R + 1];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) q[k][j] = Elem<Store::F32>::ld4(U + off[k] + (long long)zclamp(c0 - 2 * R + j) * plane);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) w[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // The E2 ring of plane z belongs to neighbour tiles, which fetch plane z
+    // as their queue front R planes before this tile stages it; it is loaded
+    // with this tile's own fronts (plane zl + R), when the neighbours' fetch
+    // can serve it from L2, and parked in LDS slot (iteration + R) mod (R+1)
+    // until staged.  The first R planes are parked here.
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int k = 0; k < HP2; ++k)
+            if (h2i[k] >= 0)
+                park[j * K::NR2 + k * kBlock + lane] = Elem<Store::F32>::ld4(U + hoff[k] + (long long)zclamp(zl0 + j) * plane);
+#pragma unroll
+    for (int j = 0; j <= R; ++j) pq[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    struct Pre {
+        float4 front[NS], mv[NS], pv[NS], h2[HP2];
+    };
+    // u^{n-1} and p use ordinary loads: the ring's values are read by the
+    // neighbour tiles in the same plane step, and their fetch should find
+    // the line in L2 (non-temporal loads here doubled the bytes read).
+    auto issue = [&](Pre &r, int it) __attribute__((always_inline)) {
+        it = min(it, npl - 1);   // past the chunk: a harmless in-bounds reload
+        const int zl = zl0 + it;
+        const long long fo = (long long)zclamp(zl + R) * plane, zo = (long long)zclamp(zl) * plane;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            r.front[k] = Elem<Store::F32>::ld4(U + off[k] + fo);
+            r.mv[k] = Elem<Store::F32>::ld4(Pv + off[k] + zo);
+            r.pv[k] = Elem<Store::F32>::ld4(Pp + off[k] + zo);
+        }
+#pragma unroll
+        for (int k = 0; k < HP2; ++k) r.h2[k] = Elem<Store::F32>::ld4(U + hoff[k] + fo);
+    };
+
+    // The Laplacian of one group: x neighbours from an LDS row (the group's
+    // own value xc in the middle), y neighbours j rows up and down, z from
+    // the queue; the same fused multiply-adds in the same order as the
+    // one-step kernel.
+    auto laplace = [&](const float4 *row, int rowpitch, const float4 &xc, const float4 *zq, float lap[4])
+        __attribute__((always_inline)) {
+        float xs[4 * (2 * HX4 + 1)];
+#pragma unroll
+        for (int c = -HX4; c <= HX4; ++c) {
+            const float4 v = (c == 0) ? xc : row[c];
+            xs[4 * (c + HX4) + 0] = v.x;
+            xs[4 * (c + HX4) + 1] = v.y;
+            xs[4 * (c + HX4) + 2] = v.z;
+            xs[4 * (c + HX4) + 3] = v.w;
+        }
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const float4 yp = row[j * rowpitch], ym = row[-j * rowpitch];
+            const float4 zp = zq[R + j], zm = zq[R - j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float xsum = xs[4 * HX4 + i + j] + xs[4 * HX4 + i - j];
+                lap[i] = j == 1 ? a.wx[1] * xsum : __builtin_fmaf(a.wx[j], xsum, lap[i]);
+                lap[i] = __builtin_fmaf(a.wy[j], comp(yp, i) + comp(ym, i), lap[i]);
+                lap[i] = __builtin_fmaf(a.wz[j], comp(zp, i) + comp(zm, i), lap[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lap[i] = __builtin_fmaf(a.w0, xs[4 * HX4 + i], lap[i]);
+    };
+
+    auto body = [&](int it, const Pre &cur, Pre &nxt) __attribute__((always_inline)) {
+        const int zl = zl0 + it;
+        float4 *st = stg + (it & 1) * N2;
+        float *s_src1 = reinterpret_cast<float *>(stg + ((it + 1) & 1) * N2);   // idle this plane
+        float4 *park_w = park + ((it + R) % (R + 1)) * K::NR2 + lane;
+        const float4 *park_r = park + (it % (R + 1)) * K::NR2 + lane;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            q[k][2 * R] = cur.front[k];
+            if (e1i[k] >= 0) st[e2i[k]] = q[k][R];
+        }
+#pragma unroll
+        for (int k = 0; k < HP2; ++k) {
+            if (h2i[k] >= 0) {
+                park_w[k * kBlock] = cur.h2[k];
+                st[h2i[k]] = park_r[k * kBlock];
+            }
+        }
+        issue(nxt, it + 1);
+        // sources: level 1 at plane zl (the extended tables, row n), level 2
+        // at plane zl - R (the tile's points of the same tables, row n + 1)
+        const bool lev2 = it >= 2 * R;
+        const int e0 = __builtin_amdgcn_readfirstlane(s_pp[it]);
+        const int e1 = __builtin_amdgcn_readfirstlane(s_pp[it + 1]);
+        const int f0 = lev2 ? __builtin_amdgcn_readfirstlane(s_pp[it - R]) : 0;
+        const int f1 = lev2 ? __builtin_amdgcn_readfirstlane(s_pp[it - R + 1]) : 0;
+        if (e0 < e1) {
+            // The buffer held the previous plane's staged values: every wave
+            // is past reading them, then it is cleared.  (On such a plane
+            // the barrier at its end keeps the next plane's staging from
+            // overwriting the terms before they are read.)
+            __syncthreads();
+            for (int i = lane; i < N1; i += kBlock) reinterpret_cast<float4 *>(s_src1)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            __syncthreads();
+            for (int e = e0 + lane; e < e1; e += kBlock) {
+                const int4 c = a.inj.corner[e];
+                float v = 0.f;
+                for (int k = c.z; k < c.w; ++k) v = __builtin_fmaf(a.inj.w[k], a.inj.vals[a.inj.src[k]], v);
+                s_src1[(c.y - (y0 - R)) * (4 * W1) + (c.x - (x0 - 4 * HX4))] = v * a.inj.scale;
+            }
+        }
+        if (f0 < f1) {
+            for (int e = f0 + lane; e < f1; e += kBlock) {
+                const int4 c = a.inj.corner[e];
+                if (c.x >= x0 && c.x < x0 + 4 * TW && c.y >= y0 && c.y < y0 + TY) {
+                    float v = 0.f;
+                    for (int k = c.z; k < c.w; ++k) v = __builtin_fmaf(a.inj2.w[k], a.inj2.vals[a.inj2.src[k]], v);
+                    reinterpret_cast<float *>(s_src2)[(c.y - y0) * (4 * TW) + (c.x - x0)] = v * a.inj2.scale;
+                }
+            }
+        }
+        __syncthreads();
+        // level 1 on every slot of the lane, zero outside the grid
+        const bool in_z = zl >= 0 && zl < L.nz;
+        const float sz1 = s_dz[it];
+        float4 *rw = ring + (it % (R + 1)) * N1;
+        float4 v1[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            v1[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k == 0 || e1i[k] >= 0) {
+                float lap[4];
+                laplace(st + e2i[k], W2, q[k][R], q[k], lap);
+                float4 src4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (e0 < e1 && e1i[k] >= 0) src4 = reinterpret_cast<const float4 *>(s_src1)[e1i[k]];
+                const float src[4] = {src4.x, src4.y, src4.z, src4.w};
+                float un[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float u1 = update_point(comp(q[k][R], i), comp(cur.mv[k], i), comp(cur.pv[k], i), lap[i],
+                                                  src[i], sxy[k][i] + sz1);
+                    un[i] = (in_z && in1[k] && gxs[k] + i < L.nx) ? u1 : 0.f;
+                }
+                asm volatile("" ::"v"(un[0]), "v"(un[1]), "v"(un[2]), "v"(un[3]));
+                v1[k] = make_float4(un[0], un[1], un[2], un[3]);
+            }
+            if (e1i[k] >= 0) rw[e1i[k]] = v1[k];
+        }
+        w[2 * R] = v1[0];
+        pq[R] = cur.pv[0];
+        // u^{n+1} of the tile, for the planes of this chunk
+        if (act && zl >= c0 && zl < c1) {
+            const long long o = off[0] + (long long)zl * plane;
+            if (nvalid >= 4) {
+                st4nt_f32(O1 + o, v1[0]);
+            } else {
+                const float rv[3] = {v1[0].x, v1[0].y, v1[0].z};
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    if (i < nvalid) O1[o + i] = rv[i];
+            }
+        }
+        // level 2 at plane zl - R: x and y neighbours from the u^{n+1} plane
+        // written R iterations ago, z from the lane's queue, u^n from the
+        // bottom of its u^n queue
+        if (lev2) {
+            float4 src4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (f0 < f1) {
+                src4 = s_src2[lane];
+                s_src2[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            if (act) {
+                const float4 *rr = ring + ((it - R) % (R + 1)) * N1 + e1i[0];
+                float lap[4];
+                laplace(rr, W1, w[R], w, lap);
+                const float src[4] = {src4.x, src4.y, src4.z, src4.w};
+                const float sz2 = s_dz[it - R];
+                float un[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    un[i] = update_point(comp(w[R], i), comp(q[0][0], i), comp(pq[0], i), lap[i], src[i],
+                                         sxy[0][i] + sz2);
+                asm volatile("" ::"v"(un[0]), "v"(un[1]), "v"(un[2]), "v"(un[3]));
+                const long long o = off[0] + (long long)(zl - R) * plane;
+                if (nvalid >= 4) {
+                    st4nt_f32(O2 + o, make_float4(un[0], un[1], un[2], un[3]));
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        if (i < nvalid) O2[o + i] = un[i];
+                }
+            }
+        }
+        if (e0 < e1 || f0 < f1) __syncthreads();   // read (and level 2's cleared) before the buffers are reused
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) q[k][j] = q[k][j + 1];
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) w[j] = w[j + 1];
+#pragma unroll
+        for (int j = 0; j < R; ++j) pq[j] = pq[j + 1];
+    };
+
+    __syncthreads();   // staged tables and cleared source buffers, before the first plane
+    Pre p0, p1;
+    issue(p0, 0);
+    int it = 0;
+    for (; it + 2 <= npl; it += 2) {
+        body(it, p0, p1);
+        body(it + 1, p1, p0);
+    }
+    if (it < npl) body(it, p0, p1);
+}
+
 // ------------------------------------------------------------------ 2D step
 // Grid axes (x, z); tile 64 x 64 staged whole in LDS with an r halo; each
 // lane computes 4 x points in each of 4 rows.
@@ -1119,6 +1489,34 @@ inline int grid_for(long long n) {
 }
 
 }  // namespace
+
+hipError_t launch_step_t2(const StepArgs &a, hipStream_t s) {
+    void (*f)(const StepArgs) = nullptr;
+    switch (a.L.r) {
+        case 1: f = k_step3d_t2<1>; break;
+        case 2: f = k_step3d_t2<2>; break;
+        case 3: f = k_step3d_t2<3>; break;
+        case 4: f = k_step3d_t2<4>; break;
+        default: return hipErrorInvalidValue;
+    }
+    if (a.L.ndim != 3) return hipErrorInvalidValue;
+    const int blocks = a.ntx * a.nty * a.ntz + a.nsamp_blocks + a.nsamp_blocks2;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int step_t2_blocks_per_cu(int r) {
+    const void *f = r == 1 ? reinterpret_cast<const void *>(k_step3d_t2<1>)
+                    : r == 2 ? reinterpret_cast<const void *>(k_step3d_t2<2>)
+                    : r == 3 ? reinterpret_cast<const void *>(k_step3d_t2<3>)
+                    : r == 4 ? reinterpret_cast<const void *>(k_step3d_t2<4>)
+                             : nullptr;
+    if (!f) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, 0) != hipSuccess) return 0;
+    return n;
+}
 
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s) {
     StepFn f = pick_step(a.L.ndim, a.L.r, st, mode, a.shape3);

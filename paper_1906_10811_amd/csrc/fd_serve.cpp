@@ -1,17 +1,20 @@
 // fd_serve.cpp -- continuous-batching shot server of libfd.
 //
-// One scheduler thread owns a device arena of hbm_budget_bytes.  Submitted
-// requests wait in FIFO order; a request is admitted as soon as a slot is
-// free and a first-fit block of the arena can hold its footprint (its grid
-// workspace, wavelets and traces).  Every admitted request keeps its
-// wavefields resident on its own stream; each scheduler round enqueues the
-// next chunk of steps of every resident request, so the device interleaves
-// the kernels of all resident shots, and a request arriving while others run
-// starts without waiting for them to finish.  Completion is detected with
-// events; the traces are copied out, the block is returned to the arena and
-// the ticket is signalled.  Each request runs the same kernels with the same
-// launch geometry as a lone fd_forward, so its result does not depend on the
-// mix it ran in.
+// The server owns a device arena of hbm_budget_bytes and two host threads.
+// Submitted requests wait in FIFO order.  The admission thread admits the
+// head request as soon as a slot is free and a first-fit block of the arena
+// can hold its footprint (its grid workspace, velocity, wavelets and
+// traces), uploads its inputs and creates its grid on the request's own
+// stream, and hands it to the scheduler; it also finishes completed
+// requests (traces copied out, block returned to the arena, ticket
+// signalled), which may admit the next one.  The scheduler thread only
+// enqueues: each round it enqueues the next chunk of steps of every resident
+// request whose previous chunk has completed (an event per request), so the
+// device interleaves the kernels of all resident shots, and neither an
+// admission (host-to-device copies, grid set-up, which synchronises the new
+// request's stream) nor a completion stalls the shots already running.
+// Each request runs the same kernels with the same launch geometry as a
+// lone fd_forward, so its result does not depend on the mix it ran in.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -124,11 +127,13 @@ struct fd_server {
     Arena *arena = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<bool> slot_busy;
-    std::thread worker;
+    std::thread scheduler, admitter;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Req *> pending;
-    std::vector<Req *> active;
+    std::condition_variable cv_admit, cv_sched, cv_done;
+    std::deque<Req *> pending;     // submitted, not admitted (FIFO)
+    std::deque<Req *> ready;       // admitted and set up, not yet picked up by the scheduler
+    std::deque<Req *> finishing;   // last chunk completed (or failed), to be finished
+    int inflight = 0;              // admitted and not yet finished
     std::map<uint64_t, Req *> done;
     std::set<uint64_t> live;   // tickets submitted and not yet collected by fd_wait
     bool stopping = false;
@@ -140,9 +145,12 @@ struct fd_server {
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    void run();
+    bool drained() const { return stopping && pending.empty() && inflight == 0; }
+    void run_scheduler();
+    void run_admitter();
     int admit(Req *r);
     void finish(Req *r, int status);
+    void to_finishing(Req *r, int status);
 };
 
 int fd_server::admit(Req *r) {
@@ -166,7 +174,9 @@ int fd_server::admit(Req *r) {
 }
 
 void fd_server::finish(Req *r, int status) {
-    if (status != FD_OK) r->msg = fd_last_error();
+    // (a failure reported by the scheduler thread carries its message already;
+    // the error text is thread-local)
+    if (status != FD_OK && r->msg.empty()) r->msg = fd_last_error();
     if (r->grid && status == FD_OK) {
         hipStream_t s = streams[r->slot];
         if (hipMemcpyAsync(r->rec_out_host, r->d_rec, sizeof(float) * (size_t)r->nt * r->nrec,
@@ -185,6 +195,8 @@ void fd_server::finish(Req *r, int status) {
         arena->release(r->off, r->fp.total);
         slot_busy[r->slot] = false;
         r->slot = -1;
+        --inflight;
+        cv_sched.notify_all();   // (drain check of a stopping scheduler)
     }
     r->res.status = status;
     r->res.t_done = now();
@@ -197,103 +209,136 @@ void fd_server::finish(Req *r, int status) {
     cv_done.notify_all();
 }
 
-void fd_server::run() {
+// Hand a request whose run ended (status FD_OK after its last chunk, or an
+// error) to the admission thread, which finishes it.
+void fd_server::to_finishing(Req *r, int status) {
+    if (status != FD_OK) r->msg = fd_last_error();
+    r->res.status = status;
+    std::lock_guard<std::mutex> lk(mu);
+    finishing.push_back(r);
+    cv_admit.notify_all();
+}
+
+void fd_server::run_admitter() {
     (void)hipSetDevice(d.device);
-    const int chunk = d.steps_per_round > 0 ? d.steps_per_round : 50;
     for (;;) {
-        std::vector<Req *> admitted, rejected;
+        Req *fin = nullptr, *adm = nullptr, *rej = nullptr;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (active.empty() && pending.empty()) {
-                if (stopping) return;
-                cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
-                if (pending.empty() && stopping) return;
-            }
-            // admission: FIFO, by slot and by arena space
-            while (!pending.empty()) {
-                Req *r = pending.front();
-                if (r->fp.total > d.hbm_budget_bytes || r->fp.total == 0) {
-                    pending.pop_front();
-                    rejected.push_back(r);
-                    continue;
+            for (;;) {
+                if (!finishing.empty()) {
+                    fin = finishing.front();
+                    finishing.pop_front();
+                    break;
                 }
-                if ((int)active.size() >= d.max_slots) break;
-                size_t off = 0;
-                if (!arena->alloc(r->fp.total, &off)) break;
-                int slot = -1;
-                for (int i = 0; i < d.max_slots; ++i)
-                    if (!slot_busy[i]) { slot = i; break; }
-                slot_busy[slot] = true;
-                r->off = off;
-                r->slot = slot;
-                r->res.t_start = now();
-                pending.pop_front();
-                active.push_back(r);
-                admitted.push_back(r);
-                peak_bytes = std::max(peak_bytes, arena->used());
-                peak_slots = std::max(peak_slots, (int)active.size());
+                if (!pending.empty()) {
+                    Req *r = pending.front();
+                    if (r->fp.total > d.hbm_budget_bytes || r->fp.total == 0) {
+                        pending.pop_front();
+                        rej = r;
+                        break;
+                    }
+                    // FIFO: the head waits for a slot and for arena space
+                    size_t off = 0;
+                    if (inflight < d.max_slots && arena->alloc(r->fp.total, &off)) {
+                        int slot = -1;
+                        for (int i = 0; i < d.max_slots; ++i)
+                            if (!slot_busy[i]) {
+                                slot = i;
+                                break;
+                            }
+                        slot_busy[slot] = true;
+                        r->off = off;
+                        r->slot = slot;
+                        r->res.t_start = now();
+                        pending.pop_front();
+                        ++inflight;
+                        peak_bytes = std::max(peak_bytes, arena->used());
+                        peak_slots = std::max(peak_slots, inflight);
+                        adm = r;
+                        break;
+                    }
+                }
+                if (drained()) {
+                    cv_sched.notify_all();
+                    return;
+                }
+                cv_admit.wait(lk);
             }
         }
-        for (Req *r : rejected) finish(r, fdi_fail(FD_ERR_NOMEM, "request needs %zu bytes > budget", r->fp.total));
-        for (Req *r : admitted) {
-            int rc = admit(r);
+        if (fin) {
+            finish(fin, fin->res.status);
+        } else if (rej) {
+            finish(rej, fdi_fail(FD_ERR_NOMEM, "request needs %zu bytes > budget", rej->fp.total));
+        } else if (adm) {
+            const int rc = admit(adm);
             if (rc) {
-                {
-                    std::lock_guard<std::mutex> lk(mu);
-                    active.erase(std::find(active.begin(), active.end(), r));
-                }
-                finish(r, rc);
+                finish(adm, rc);
+            } else {
+                std::lock_guard<std::mutex> lk(mu);
+                ready.push_back(adm);
+                cv_sched.notify_all();
             }
         }
-        // one round: next chunk of every resident request whose previous chunk is done
-        bool progressed = !admitted.empty();
-        std::vector<Req *> act;
+    }
+}
+
+void fd_server::run_scheduler() {
+    (void)hipSetDevice(d.device);
+    const int chunk = d.steps_per_round > 0 ? d.steps_per_round : 50;
+    std::vector<Req *> active;
+    for (;;) {
         {
-            std::lock_guard<std::mutex> lk(mu);
-            act = active;
+            std::unique_lock<std::mutex> lk(mu);
+            if (active.empty()) cv_sched.wait(lk, [&] { return !ready.empty() || drained(); });
+            if (active.empty() && ready.empty() && drained()) return;
+            while (!ready.empty()) {
+                active.push_back(ready.front());
+                ready.pop_front();
+            }
         }
-        for (Req *r : act) {
+        // one round: the next chunk of every resident request whose previous
+        // chunk is done; a request past its last step goes to finishing
+        bool progressed = false;
+        for (size_t i = 0; i < active.size();) {
+            Req *r = active[i];
+            int status = FD_OK;
+            bool ended = false;
             if (r->ev_pending) {
                 const hipError_t q = hipEventQuery(r->ev);
-                if (q == hipErrorNotReady) continue;
-                r->ev_pending = false;
-                if (q != hipSuccess) {
-                    {
-                        std::lock_guard<std::mutex> lk(mu);
-                        active.erase(std::find(active.begin(), active.end(), r));
-                    }
-                    finish(r, fdi_fail(FD_ERR_DEVICE, "request %llu: %s", (unsigned long long)r->ticket,
-                                       hipGetErrorString(q)));
-                    progressed = true;
+                if (q == hipErrorNotReady) {
+                    ++i;
                     continue;
                 }
-            }
-            if (r->next_step >= r->nt) {
-                {
-                    std::lock_guard<std::mutex> lk(mu);
-                    active.erase(std::find(active.begin(), active.end(), r));
+                r->ev_pending = false;
+                if (q != hipSuccess) {
+                    status = fdi_fail(FD_ERR_DEVICE, "request %llu: %s", (unsigned long long)r->ticket,
+                                      hipGetErrorString(q));
+                    ended = true;
                 }
-                finish(r, FD_OK);
-                progressed = true;
-                continue;
             }
-            hipStream_t s = streams[r->slot];
-            fd_shot sh{r->nsrc, r->src.data(), r->d_wav, r->nrec, r->rec.data()};
-            const int n1 = std::min(r->nt, r->next_step + chunk);
-            int rc = fdi_forward_steps(r->grid, &sh, r->nt, r->next_step, n1, r->d_rec, nullptr, 1, s);
-            if (rc == FD_OK && hipEventRecord(r->ev, s) != hipSuccess) rc = FD_ERR_DEVICE;
-            if (rc) {
-                {
-                    std::lock_guard<std::mutex> lk(mu);
-                    active.erase(std::find(active.begin(), active.end(), r));
+            if (!ended && r->next_step >= r->nt) ended = true;
+            if (!ended) {
+                hipStream_t s = streams[r->slot];
+                fd_shot sh{r->nsrc, r->src.data(), r->d_wav, r->nrec, r->rec.data()};
+                const int n1 = std::min(r->nt, r->next_step + chunk);
+                status = fdi_forward_steps(r->grid, &sh, r->nt, r->next_step, n1, r->d_rec, nullptr, 1, s);
+                if (status == FD_OK && hipEventRecord(r->ev, s) != hipSuccess)
+                    status = fdi_fail(FD_ERR_DEVICE, "event record failed");
+                if (status == FD_OK) {
+                    r->next_step = n1;
+                    r->ev_pending = true;
+                } else {
+                    ended = true;
                 }
-                finish(r, rc);
-                progressed = true;
-                continue;
             }
-            r->next_step = n1;
-            r->ev_pending = true;
             progressed = true;
+            if (ended) {
+                active.erase(active.begin() + (long)i);
+                to_finishing(r, status);
+            } else {
+                ++i;
+            }
         }
         if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
@@ -340,7 +385,8 @@ extern "C" int fd_server_create(const fd_server_desc *desc, fd_server **out) {
             }
         }
         (void)hipSetDevice(prev);
-        srv->worker = std::thread([srv] { srv->run(); });
+        srv->scheduler = std::thread([srv] { srv->run_scheduler(); });
+        srv->admitter = std::thread([srv] { srv->run_admitter(); });
         *out = srv;
         return FD_OK;
     } catch (const std::bad_alloc &) {
@@ -399,7 +445,7 @@ extern "C" int fd_submit(fd_server *srv, const fd_request *req, uint64_t *ticket
         srv->live.insert(r->ticket);
         srv->pending.push_back(r);
         *ticket = r->ticket;
-        srv->cv_work.notify_one();
+        srv->cv_admit.notify_all();
         return FD_OK;
     } catch (const std::bad_alloc &) {
         return fdi_fail(FD_ERR_NOMEM, "host allocation failed");
@@ -448,9 +494,11 @@ extern "C" int fd_server_destroy(fd_server *srv) {
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stopping = true;
-        srv->cv_work.notify_all();
+        srv->cv_admit.notify_all();
+        srv->cv_sched.notify_all();
     }
-    if (srv->worker.joinable()) srv->worker.join();
+    if (srv->admitter.joinable()) srv->admitter.join();
+    if (srv->scheduler.joinable()) srv->scheduler.join();
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(srv->d.device);

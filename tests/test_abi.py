@@ -43,6 +43,7 @@ def _desc(**kw):
     d.nbl = kw.get("nbl", 10)
     d.storage = kw.get("storage", 0)
     d.tile_x = kw.get("tile_x", 0)
+    d.time_block = kw.get("time_block", 0)
     return d
 
 
@@ -64,11 +65,22 @@ def test_workspace_bytes_grow_with_grid(lib):
     for tx in (32, 64, 96):
         rc4, b4 = _bytes(lib, _desc(shape=(64, 48, 32), tile_x=tx))
         assert rc4 == 0 and b4 > 0
+    # two levels per launch (on request) keep two more wavefield buffers
+    # than one step (the automatic choice)
+    rc5, b5 = _bytes(lib, _desc(shape=(64, 48, 32), time_block=1))
+    rc6, b6 = _bytes(lib, _desc(shape=(64, 48, 32), time_block=2))
+    assert rc5 == 0 and rc6 == 0 and b5 == b1
+    assert b6 - b5 >= 2 * 4 * (84 * 68 * 52)
+    rc7, b7 = _bytes(lib, _desc(shape=(64, 48, 32), so=10))
+    rc8, b8 = _bytes(lib, _desc(shape=(64, 48, 32), so=10, time_block=1))
+    assert rc7 == 0 and b7 == b8
 
 
 @pytest.mark.parametrize("bad", [
     dict(ndim=4), dict(so=3), dict(so=18), dict(so=0), dict(nbl=-1), dict(shape=(1, 8, 8)),
     dict(storage=7), dict(tile_x=48), dict(tile_x=-32), dict(tile_x=128),
+    dict(time_block=3), dict(time_block=-1), dict(time_block=2, storage=2), dict(time_block=2, so=10),
+    dict(time_block=2, ndim=2),
 ])
 def test_invalid_descriptors_rejected(lib, bad):
     rc, _ = _bytes(lib, _desc(**bad))

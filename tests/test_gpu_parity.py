@@ -43,7 +43,7 @@ def test_acoustic2d_101_workload():
 @pytest.mark.parametrize("zchunk", [0, 7])
 @pytest.mark.parametrize("tile_x", [64, 32, 96])
 def test_3d_every_space_order(so, zchunk, tile_x):
-    """70x37x29 + 5-point layer (80 x 47 x 39 padded): 64 x 16 tiles give 2
+    """One step per launch.  70x37x29 + 5-point layer (80 x 47 x 39 padded): 64 x 16 tiles give 2
     x tiles and 3 y tiles, 32 x 32 tiles 3 and 2, all ragged; the mixed
     shape (96) one 64 x 16 column of 3 tiles and a 16-point strip of two
     32 x 32 tiles (so 14 and 16: 32 x 32 throughout); z chunks of 7 or
@@ -51,7 +51,7 @@ def test_3d_every_space_order(so, zchunk, tile_x):
     need_gpu()
     c = case((70, 37, 29), so, 5, 60, seed=so, nsrc=3, nrec=9)
     want, u_nt, _, _ = oracle_forward(c)
-    g = gpu_grid(c, zchunk=zchunk, tile_x=tile_x)
+    g = gpu_grid(c, zchunk=zchunk, tile_x=tile_x, time_block=1)
     _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
     assert_traces(rec.cpu().numpy(), want, TOL, "3d so=%d zchunk=%d tile_x=%d" % (so, zchunk, tile_x))
     assert_field(state[0].cpu().numpy(), u_nt, TOL, "3d so=%d zchunk=%d tile_x=%d" % (so, zchunk, tile_x))

@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 def _shapes(c, shapes=(64, 32, 96), **kw):
     out = []
+    kw.setdefault("time_block", 1)   # the one-step kernel, whose tile shape is chosen
     for tx in shapes:
         g = gpu_grid(c, tile_x=tx, **kw)
         assert g.tile == ((32, 32) if tx == 32 else (64, 16))
@@ -53,7 +54,7 @@ def test_narrow_tiles_against_oracle_many_sources():
     c = case((75, 69, 28), 8, 4, 40, seed=77, nsrc=12, nrec=9)
     c["sinc"] = 3
     want, u_nt, _, _ = oracle_forward(c)
-    g = gpu_grid(c, tile_x=32)
+    g = gpu_grid(c, tile_x=32, time_block=1)
     _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
     e_rec = rel_l2(rec.cpu().numpy(), want)
     e_u = rel_l2(state[0].cpu().numpy(), u_nt)

@@ -1,0 +1,141 @@
+"""Two leapfrog levels per launch (time_block 2, k_step3d_t2) against one
+step per launch (time_block 1) and against the FP64 oracle.
+
+Each level of the two-level kernel is the same sequence of float32
+operations as the one-step kernel's, on the same inputs (level-1 values of
+the recomputed ring included, and zero outside the grid), so traces and
+fields must be bitwise equal to one step per launch.  The cases cover every
+radius it runs (space orders 2-8), ragged 64 x 16 tiles, short z chunks
+(level-1 planes recomputed at every chunk seam), odd step counts (a last
+one-step launch), sources on tile seams and inside the recomputed ring of a
+neighbour tile, windowed-sinc nodes spread over several tiles, a caller's
+initial state, and runs resumed from a saved state.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import assert_field, assert_traces, case, gpu_forward, gpu_grid, need_gpu, oracle_forward, torch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _both(c, **kw):
+    out = []
+    for tb in (1, 2):
+        g = gpu_grid(c, time_block=tb, **kw)
+        assert g.time_block == tb
+        _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
+        out.append((rec, state))
+        g.close()
+    return out
+
+
+def _seam_sources(c, n):
+    """n sources around the seams of the 64 x 16 tiles (padded x near 64 and
+    128, y near 16 and 32) and inside a neighbour's ring."""
+    h, o, nbl = c["spacing"], c["origin"], c["nbl"]
+    px = [62.6, 63.5, 64.0, 65.3, 67.9, 127.2, 60.1, 66.4]
+    py = [15.4, 16.0, 17.5, 12.9, 19.8, 31.6, 32.3, 14.1]
+    pz = [5.2, 9.9, 14.0, 20.5, 7.7, 25.3, 11.1, 3.6]
+    out = []
+    for k in range(n):
+        x = min(px[k] - nbl, c["shape"][0] - 1.0)
+        y = min(py[k] - nbl, c["shape"][1] - 1.0)
+        z = min(pz[k] - nbl + 2, c["shape"][2] - 1.0)
+        out.append((o[0] + max(x, 0.0) * h[0], o[1] + max(y, 0.0) * h[1], o[2] + max(z, 0.0) * h[2]))
+    return out
+
+
+@pytest.mark.parametrize("so", [2, 4, 6, 8])
+@pytest.mark.parametrize("nt,zchunk", [(60, 0), (61, 0), (47, 5)])
+def test_two_levels_bitwise_equal_one_step(so, nt, zchunk):
+    """130 x 45 x 37 + 4 (138 x 53 x 45 padded): 3 tile columns (the last 10
+    points wide) x 4 ragged tile rows; 8 sources on and around tile seams,
+    11 receivers; even and odd step counts, automatic and 5-plane chunks."""
+    need_gpu()
+    c = case((130, 45, 37), so, 4, nt, seed=60 + so, nsrc=8, nrec=11)
+    c["src"] = _seam_sources(c, 8)
+    (r1, s1), (r2, s2) = _both(c, zchunk=zchunk)
+    same = bool(torch.equal(r1, r2) and torch.equal(s1[0], s2[0]) and torch.equal(s1[1], s2[1]))
+    print("time_block 2 vs 1, so %d nt %d zchunk %d: bitwise %d" % (so, nt, zchunk, int(same)), flush=True)
+    assert torch.equal(r1, r2)
+    assert torch.equal(s1[0], s2[0]) and torch.equal(s1[1], s2[1])
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_two_levels_against_oracle(so):
+    need_gpu()
+    c = case((130, 45, 37), so, 5, 71, seed=70 + so, nsrc=5, nrec=9)
+    c["src"] = _seam_sources(c, 5)
+    want, u_nt, u_prev, _ = oracle_forward(c)
+    g = gpu_grid(c, time_block=2)
+    _, (rec, state) = gpu_forward(c, grid=g, save_state=True)
+    assert_traces(rec.cpu().numpy(), want, TOL, "time_block 2 so %d" % so)
+    assert_field(state[0].cpu().numpy(), u_nt, TOL, "time_block 2 so %d, u^nt" % so)
+    assert_field(state[1].cpu().numpy(), u_prev, TOL, "time_block 2 so %d, u^(nt-1)" % so)
+
+
+@pytest.mark.parametrize("sinc", [2, 4])
+def test_two_levels_sinc_points_across_tiles(sinc):
+    """Windowed-sinc sources (up to 8^3 nodes each) straddling tile seams:
+    their nodes fall in the recomputed rings of several tiles."""
+    need_gpu()
+    c = case((100, 40, 30), 8, 4, 44, seed=80 + sinc, nsrc=6, nrec=7)
+    c["src"] = _seam_sources(c, 6)
+    c["sinc"] = sinc
+    (r1, s1), (r2, s2) = _both(c)
+    assert torch.equal(r1, r2) and torch.equal(s1[0], s2[0])
+    want, u_nt, _, _ = oracle_forward(c)
+    assert_traces(r2.cpu().numpy(), want, TOL, "time_block 2 sinc %d" % sinc)
+    assert_field(s2[0].cpu().numpy(), u_nt, TOL, "time_block 2 sinc %d" % sinc)
+
+
+def test_two_levels_thin_grids_and_resume():
+    """Grids thinner than a tile and than the level-1 ring (3 x 2 x 2 + 1,
+    nz' = 4 < 2R at so 8), and 33 + 28 resumed steps against 61 in one run."""
+    need_gpu()
+    for shape, nbl in (((3, 2, 2), 1), ((9, 40, 6), 2)):
+        c = case(shape, 8, nbl, 21, seed=5, nsrc=1, nrec=3)
+        (r1, s1), (r2, s2) = _both(c)
+        assert torch.equal(r1, r2) and torch.equal(s1[0], s2[0]), shape
+    c = case((70, 33, 26), 8, 4, 61, seed=11, nsrc=2, nrec=6)
+    dev = torch.device("cuda:0")
+    g = gpu_grid(c, time_block=2)
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    full = g.forward(c["src"], wav, c["rec"], c["dt"])
+    ra, st = g.forward(c["src"], wav[:33].contiguous(), c["rec"], c["dt"], save_state=True)
+    rb = g.forward(c["src"], wav[33:].contiguous(), c["rec"], c["dt"], u0=st[0], u_prev=st[1])
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat([ra, rb]), full)
+    rng = np.random.default_rng(3)
+    u0 = rng.standard_normal(c["og"].array_shape) * 1e-3
+    um = 0.98 * u0
+    c["nt"] = 25
+    c["wav"] = c["wav"][:25].copy()
+    want, u_nt, _, _ = oracle_forward(c, u0=u0, u_prev=um)
+    rec, state = g.forward(c["src"], torch.from_numpy(c["wav"]).to(dev), c["rec"], c["dt"],
+                           u0=torch.from_numpy(u0).float().to(dev), u_prev=torch.from_numpy(um).float().to(dev),
+                           save_state=True)
+    torch.cuda.synchronize()
+    assert_traces(rec.cpu().numpy(), want, TOL, "time_block 2, caller state")
+    assert_field(state[0].cpu().numpy(), u_nt, TOL, "time_block 2, caller state")
+
+
+def test_two_levels_through_the_server():
+    """The server advances requests in chunks of steps (an odd chunk leaves a
+    one-step launch and rows sampled across chunks): bitwise the lone
+    fd_forward with two levels per launch."""
+    need_gpu()
+    from paper_1906_10811_amd import Server
+    c = case((70, 40, 30), 8, 5, 57, seed=17, nsrc=1, nrec=9)
+    g = gpu_grid(c, time_block=2)
+    _, alone = gpu_forward(c, grid=g)
+    g.close()
+    srv = Server(1 << 30, max_slots=2, steps_per_round=7)
+    kw = dict(shape=c["shape"], spacing=c["spacing"], origin=c["origin"], space_order=c["so"], nbl=c["nbl"],
+              vp=c["v"], src_xyz=c["src"], wavelet=c["wav"], rec_xyz=c["rec"], dt=c["dt"], time_block=2)
+    out, info = srv.wait(srv.submit(**kw), timeout=120.0)
+    srv.close()
+    assert info["status"] == 0
+    assert np.array_equal(out, alone.cpu().numpy())
