@@ -395,6 +395,9 @@ def bench_serving(torch, n=64, slots=6, budget_gib=2.0, roomy_gib=32.0):
                           (the budget does not bind);
       batched_budget      the same with a budget that binds (2 GiB: about
                           three of the largest shots at once);
+      *_shortest_first    the same two with the shortest-remaining-work
+                          policy (at most two chunks on the device, for the
+                          requests with the least remaining point-steps);
       saturated_*         all requests at t = 0, one slot and `slots` slots
                           (throughput without arrival gaps)."""
     from paper_1906_10811_amd import Server
@@ -407,8 +410,8 @@ def bench_serving(torch, n=64, slots=6, budget_gib=2.0, roomy_gib=32.0):
                           vp=v, src_xyz=r["src"], wavelet=wav, rec_xyz=r["rec"], dt=r["dt"]))
     pts = sum(math.prod(s + 2 * 40 for s in r["shape"]) * r["nt"] for r in reqs)
 
-    def run(budget_gib, nslots, arrivals):
-        srv = Server(int(budget_gib * 2 ** 30), max_slots=nslots)
+    def run(budget_gib, nslots, arrivals, policy="share"):
+        srv = Server(int(budget_gib * 2 ** 30), max_slots=nslots, policy=policy)
         t0 = time.perf_counter()
         tickets = []
         for a, s in zip(arrivals, shots):
@@ -423,7 +426,7 @@ def bench_serving(torch, n=64, slots=6, budget_gib=2.0, roomy_gib=32.0):
         total = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        return dict(budget_gib=budget_gib, slots=nslots, shots_per_s=round(n / total, 3),
+        return dict(budget_gib=budget_gib, slots=nslots, policy=policy, shots_per_s=round(n / total, 3),
                     gpts=round(pts / total / 1e9, 1), p50_s=round(float(np.percentile(lat, 50)), 4),
                     p99_s=round(float(np.percentile(lat, 99)), 4), makespan_s=round(total, 3),
                     peak_gb=round(st["peak_bytes"] / 1e9, 3), peak_slots=st["peak_slots"])
@@ -439,6 +442,8 @@ def bench_serving(torch, n=64, slots=6, budget_gib=2.0, roomy_gib=32.0):
     out["fifo_one_at_a_time"] = run(roomy_gib, 1, arrivals)
     out["batched"] = run(roomy_gib, slots, arrivals)
     out["batched_budget"] = run(budget_gib, slots, arrivals)
+    out["batched_shortest_first"] = run(roomy_gib, slots, arrivals, policy="shortest")
+    out["batched_budget_shortest_first"] = run(budget_gib, slots, arrivals, policy="shortest")
     out["saturated_one_slot"] = sat1
     out["saturated_batched"] = run(roomy_gib, slots, zeros)
     return out

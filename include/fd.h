@@ -297,7 +297,18 @@ typedef struct fd_server_desc {
     size_t hbm_budget_bytes;   /* arena size; admission never exceeds it */
     int max_slots;             /* requests resident at once, >= 1 */
     int steps_per_round;       /* steps enqueued per request per scheduler round, 0 selects 50 */
+    int policy;                /* FD_SERVE_SHARE (0): every resident request gets the next chunk
+                                  of steps as soon as its previous one completes (equal shares);
+                                  FD_SERVE_SHORTEST (1): preemptive shortest remaining work
+                                  first at chunk granularity -- the device holds at most two
+                                  chunks, both for the resident request with the fewest
+                                  remaining point-steps while it has steps left (a short shot
+                                  arriving behind a long one overtakes it at the next chunk
+                                  boundary) */
 } fd_server_desc;
+
+#define FD_SERVE_SHARE 0
+#define FD_SERVE_SHORTEST 1
 
 typedef struct fd_request {
     fd_grid_desc grid;         /* grid of this shot */

@@ -288,13 +288,19 @@ def modeling(vp_padded: torch.Tensor, wavelet: torch.Tensor, shape, spacing, spa
 class Server:
     """Continuous-batching shot server (fd_server_create / fd_submit / fd_wait)."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, steps_per_round: int = 0, device: int = 0):
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, steps_per_round: int = 0, device: int = 0,
+                 policy: str = "share"):
+        """policy: "share" (every resident request advances as its previous
+        chunk completes) or "shortest" (preemptive shortest remaining work
+        first: the device holds at most two chunks, both for the request with
+        the least remaining work)."""
         lib = _lib.load()
         d = _lib.ServerDesc()
         d.device = int(device)
         d.hbm_budget_bytes = int(hbm_budget_bytes)
         d.max_slots = int(max_slots)
         d.steps_per_round = int(steps_per_round)
+        d.policy = {"share": _lib.FD_SERVE_SHARE, "shortest": _lib.FD_SERVE_SHORTEST}[policy]
         h = ctypes.c_void_p()
         _lib.check(lib.fd_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

@@ -28,6 +28,9 @@ FD_GRAD_VELOCITY = 4
 
 FD_ACT_ADVANCE, FD_ACT_STORE, FD_ACT_RESTORE, FD_ACT_YOUTURN = 1, 2, 3, 4
 
+FD_SERVE_SHARE = 0
+FD_SERVE_SHORTEST = 1
+
 # every symbol include/fd.h declares
 EXPORTS = (
     "fd_grid_workspace_bytes", "fd_grid_create", "fd_grid_destroy", "fd_grid_get_info",
@@ -101,6 +104,7 @@ class ServerDesc(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_size_t),
         ("max_slots", ctypes.c_int),
         ("steps_per_round", ctypes.c_int),
+        ("policy", ctypes.c_int),
     ]
 
 

@@ -13,8 +13,14 @@
 // device interleaves the kernels of all resident shots, and neither an
 // admission (host-to-device copies, grid set-up, which synchronises the new
 // request's stream) nor a completion stalls the shots already running.
-// Each request runs the same kernels with the same launch geometry as a
-// lone fd_forward, so its result does not depend on the mix it ran in.
+// With the shortest-work policy the scheduler keeps at most two chunks on
+// the device, both for the resident request with the fewest remaining
+// point-steps (preemptive shortest remaining work first, at chunk
+// granularity): a shot large enough to fill the GPU gains nothing from
+// sharing it, equal shares delay every shot, and this order lets short
+// shots pass long ones.  Each request runs the same kernels with the same
+// launch geometry as a lone fd_forward, so its result does not depend on the
+// mix it ran in or the policy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -112,9 +118,10 @@ struct Req {
     int slot = -1;
     fd_grid *grid = nullptr;
     float *d_wav = nullptr, *d_rec = nullptr;
+    double pts = 0;      // padded points of the grid (remaining work = pts * (nt - next_step))
     int next_step = 0;
-    hipEvent_t ev = nullptr;
-    bool ev_pending = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the chunks in flight, oldest at ev_head
+    int ev_head = 0, ev_count = 0;
     fd_result res{};
     std::string msg;   // error message of a failed request
 };
@@ -167,8 +174,12 @@ int fd_server::admit(Req *r) {
     fd_shot sh{r->nsrc, r->src.data(), r->d_wav, r->nrec, r->rec.data()};
     if ((rc = fdi_forward_prepare(r->grid, &sh, r->nt, r->dt, s))) return rc;
     if ((rc = fdi_forward_zero_state(r->grid, s))) return rc;
-    if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess)
-        return fdi_fail(FD_ERR_DEVICE, "event creation failed");
+    for (hipEvent_t &e : r->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return fdi_fail(FD_ERR_DEVICE, "event creation failed");
+    fd_grid_info info;
+    fd_grid_get_info(r->grid, &info);
+    r->pts = (double)info.padded_points;
     r->next_step = 0;
     return FD_OK;
 }
@@ -188,8 +199,10 @@ void fd_server::finish(Req *r, int status) {
     }
     if (r->grid) fd_grid_destroy(r->grid);
     r->grid = nullptr;
-    if (r->ev) (void)hipEventDestroy(r->ev);
-    r->ev = nullptr;
+    for (hipEvent_t &e : r->ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     std::lock_guard<std::mutex> lk(mu);
     if (r->slot >= 0) {
         arena->release(r->off, r->fp.total);
@@ -297,48 +310,73 @@ void fd_server::run_scheduler() {
                 ready.pop_front();
             }
         }
-        // one round: the next chunk of every resident request whose previous
-        // chunk is done; a request past its last step goes to finishing
+        // one round.  Poll the chunks in flight; a request past its last
+        // step (or failed) goes to finishing.  Then enqueue: with equal
+        // shares, the next chunk of every request whose previous chunk is
+        // done; with the shortest-work policy, chunks for the requests with
+        // the least remaining point-steps, shortest first, up to two chunks
+        // on the device (the shortest request gets both, queued back to back
+        // on its stream, so it runs alone but for the tail of its last chunk)
         bool progressed = false;
         for (size_t i = 0; i < active.size();) {
             Req *r = active[i];
             int status = FD_OK;
-            bool ended = false;
-            if (r->ev_pending) {
-                const hipError_t q = hipEventQuery(r->ev);
-                if (q == hipErrorNotReady) {
-                    ++i;
-                    continue;
-                }
-                r->ev_pending = false;
+            while (r->ev_count > 0) {
+                const hipError_t q = hipEventQuery(r->ev[r->ev_head]);
+                if (q == hipErrorNotReady) break;
+                r->ev_head ^= 1;
+                --r->ev_count;
+                progressed = true;
                 if (q != hipSuccess) {
                     status = fdi_fail(FD_ERR_DEVICE, "request %llu: %s", (unsigned long long)r->ticket,
                                       hipGetErrorString(q));
-                    ended = true;
+                    break;
                 }
             }
-            if (!ended && r->next_step >= r->nt) ended = true;
-            if (!ended) {
-                hipStream_t s = streams[r->slot];
-                fd_shot sh{r->nsrc, r->src.data(), r->d_wav, r->nrec, r->rec.data()};
-                const int n1 = std::min(r->nt, r->next_step + chunk);
-                status = fdi_forward_steps(r->grid, &sh, r->nt, r->next_step, n1, r->d_rec, nullptr, 1, s);
-                if (status == FD_OK && hipEventRecord(r->ev, s) != hipSuccess)
-                    status = fdi_fail(FD_ERR_DEVICE, "event record failed");
-                if (status == FD_OK) {
-                    r->next_step = n1;
-                    r->ev_pending = true;
-                } else {
-                    ended = true;
-                }
-            }
-            progressed = true;
-            if (ended) {
+            if (status != FD_OK || (r->ev_count == 0 && r->next_step >= r->nt)) {
                 active.erase(active.begin() + (long)i);
                 to_finishing(r, status);
+                progressed = true;
             } else {
                 ++i;
             }
+        }
+        auto enqueue = [&](Req *r) -> bool {
+            hipStream_t s = streams[r->slot];
+            fd_shot sh{r->nsrc, r->src.data(), r->d_wav, r->nrec, r->rec.data()};
+            const int n1 = std::min(r->nt, r->next_step + chunk);
+            int status = fdi_forward_steps(r->grid, &sh, r->nt, r->next_step, n1, r->d_rec, nullptr, 1, s);
+            if (status == FD_OK && hipEventRecord(r->ev[(r->ev_head + r->ev_count) & 1], s) != hipSuccess)
+                status = fdi_fail(FD_ERR_DEVICE, "event record failed");
+            progressed = true;
+            if (status != FD_OK) {
+                active.erase(std::find(active.begin(), active.end(), r));
+                // (chunks already in flight complete before finish() reads the traces)
+                to_finishing(r, status);
+                return false;
+            }
+            r->next_step = n1;
+            ++r->ev_count;
+            return true;
+        };
+        if (d.policy == FD_SERVE_SHORTEST) {
+            std::stable_sort(active.begin(), active.end(), [](const Req *x, const Req *y) {
+                return x->pts * (x->nt - x->next_step) < y->pts * (y->nt - y->next_step);
+            });
+            int budget = 2;
+            for (const Req *r : active) budget -= r->ev_count;
+            std::vector<Req *> order = active;
+            for (Req *r : order) {
+                while (budget > 0 && r->ev_count < 2 && r->next_step < r->nt) {
+                    if (!enqueue(r)) break;
+                    --budget;
+                }
+                if (budget <= 0) break;
+            }
+        } else {
+            std::vector<Req *> order = active;
+            for (Req *r : order)
+                if (r->ev_count == 0 && r->next_step < r->nt) enqueue(r);
         }
         if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
@@ -357,6 +395,8 @@ extern "C" int fd_server_create(const fd_server_desc *desc, fd_server **out) {
         *out = nullptr;
         if (desc->max_slots < 1 || desc->hbm_budget_bytes < 4096 || desc->steps_per_round < 0)
             return fdi_fail(FD_ERR_ARG, "max_slots >= 1, budget >= 4 KiB, steps_per_round >= 0");
+        if (desc->policy != FD_SERVE_SHARE && desc->policy != FD_SERVE_SHORTEST)
+            return fdi_fail(FD_ERR_ARG, "policy must be FD_SERVE_SHARE or FD_SERVE_SHORTEST");
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev)
             return fdi_fail(FD_ERR_ARG, "no such device %d", desc->device);

@@ -43,14 +43,15 @@ def _alone(r):
     return out
 
 
-def test_mix_equals_alone_and_budget_holds():
+@pytest.mark.parametrize("policy", ["share", "shortest"])
+def test_mix_equals_alone_and_budget_holds(policy):
     need_gpu()
     from paper_1906_10811_amd import Server
     reqs = _requests(9)
     alone = [_alone(r) for r in reqs]
     sizes = [Server.request_bytes(**r) for r in reqs]
     budget = int(2.2 * max(sizes))           # two of the largest, or three smaller, fit at once
-    srv = Server(budget, max_slots=3, steps_per_round=16)
+    srv = Server(budget, max_slots=3, steps_per_round=16, policy=policy)
     tickets = [srv.submit(**r) for r in reqs]
     res = [srv.wait(t, timeout=120.0) for t in tickets]
     st = srv.stats()
@@ -65,8 +66,29 @@ def test_mix_equals_alone_and_budget_holds():
     ov = sum(1 for i in range(len(res)) for j in range(i + 1, len(res))
              if res[j][1]["t_start"] < res[i][1]["t_done"] and res[i][1]["t_start"] < res[j][1]["t_done"])
     assert ov >= 1
-    print("serving: peak %.1f MB of %.1f MB budget, peak slots %d, overlapping pairs %d"
-          % (st["peak_bytes"] / 1e6, budget / 1e6, st["peak_slots"], ov))
+    print("serving (%s): peak %.1f MB of %.1f MB budget, peak slots %d, overlapping pairs %d"
+          % (policy, st["peak_bytes"] / 1e6, budget / 1e6, st["peak_slots"], ov))
+
+
+def test_shortest_policy_lets_a_short_shot_pass():
+    """With the shortest-work policy a short request submitted while a long
+    one runs completes first; with equal shares it completes later than
+    alone would take, as both progress."""
+    need_gpu()
+    from paper_1906_10811_amd import Server
+    reqs = _requests(2, seed=3)
+    long_r, short_r = dict(reqs[0]), dict(reqs[1])
+    long_r["wavelet"] = np.tile(long_r["wavelet"], (8, 1))        # 8x the steps
+    short_r["wavelet"] = short_r["wavelet"][:40].copy()
+    srv = Server(1 << 30, max_slots=2, steps_per_round=10, policy="shortest")
+    t_long = srv.submit(**long_r)
+    t_short = srv.submit(**short_r)
+    _, info_s = srv.wait(t_short, timeout=120.0)
+    _, info_l = srv.wait(t_long, timeout=120.0)
+    srv.close()
+    print("shortest policy: short done at %.4f s, long done at %.4f s" % (info_s["t_done"], info_l["t_done"]))
+    assert info_s["status"] == 0 and info_l["status"] == 0
+    assert info_s["t_done"] < info_l["t_done"]
 
 
 def test_server_result_matches_oracle():
