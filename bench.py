@@ -301,14 +301,15 @@ def bench_precision(torch, dev, stream, ref_rec):
     w, v, wav = make_workload("layered3d_256", torch, dev)
     res, recs = {}, {}
     ref = np.asarray(ref_rec, dtype=np.float64)
-    for st, scale in (("bf16", 0.0), ("f16", 0.0)):   # f16: automatic power-of-two scale
+    for st, scale in (("bf16", 0.0), ("f16", 0.0), ("bf16_diff", 0.0), ("f16_diff", 0.0)):
+        # f16: automatic power-of-two scale; *_diff: the level and its difference (12 B)
         g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, amp_scale=scale,
                  stream=stream)
         secs, rec = time_forward(torch, g, w, wav, 1, 1, stream)
         recs[st] = rec.cpu().numpy()
         err = float(np.linalg.norm(recs[st] - ref) / np.linalg.norm(ref))
         res[st] = dict(gpts=g.padded_points * w["nt"] / secs / 1e9, rel_l2_vs_f32=err,
-                       b_alg_per_pt=10, amp_scale=scale)
+                       b_alg_per_pt=12 if st.endswith("_diff") else 10, amp_scale=scale)
         g.close()
     return res, recs
 
@@ -350,12 +351,12 @@ def bench_grf512(torch, dev, stream):
     v = torch.from_numpy(v_host).to(dev)
     wav = torch.from_numpy(synth.wavelets(w)).to(dev)
     res, recs, ref = {}, {}, None
-    for st in ("f32", "f16", "bf16"):
+    for st in ("f32", "f16", "bf16", "f16_diff", "bf16_diff"):
         g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, stream=stream)
         secs, rec = time_forward(torch, g, w, wav, 1, 0, stream)
         recs[st] = rec.cpu().numpy()
         gp = g.padded_points * w["nt"] / secs / 1e9
-        b = B_STEP if st == "f32" else 10.0
+        b = B_STEP if st == "f32" else 12.0 if st.endswith("_diff") else 10.0
         res[st] = dict(gpts=round(gp, 1), frac_hbm=round(gp * b / HBM_PEAK_GBS, 4), b_alg_per_pt=b)
         if st == "f32":
             ref = recs[st].astype(np.float64)

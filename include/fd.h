@@ -73,7 +73,15 @@ typedef enum fd_status {
 typedef enum fd_storage {
     FD_STORE_F32 = 0,      /* float32 wavefields */
     FD_STORE_F16 = 1,      /* IEEE half wavefields (scaled by amp_scale), FP32 arithmetic */
-    FD_STORE_BF16 = 2      /* bfloat16 wavefields, FP32 arithmetic */
+    FD_STORE_BF16 = 2,     /* bfloat16 wavefields, FP32 arithmetic */
+    /* 16-bit value and difference (3D only; fd_forward and the server, the
+       adjoint stores two levels): u^n and u^n - u^{n-1} are kept instead of
+       two levels, so the difference -- what the leapfrog update advances --
+       keeps 16-bit relative precision where the time step is small against
+       the local period; 12 B per point-step instead of 10, three 16-bit
+       buffers */
+    FD_STORE_F16_DIFF = 3,
+    FD_STORE_BF16_DIFF = 4
 } fd_storage;
 
 /* Grid description (Devito Grid + TimeFunction, Section 2.1.1). */
@@ -87,7 +95,8 @@ typedef struct fd_grid_desc {
     double damp_max;       /* sigma_max in 1/s; <= 0 selects 3 v_max ln(1000) / (2 nbl h_min) */
     int storage;           /* fd_storage */
     float amp_scale;       /* 16-bit storage keeps amp_scale * u; 0 selects 1 for BF16 and,
-                              for F16, the power of two nearest prod(h)/(dt^2 v_max^2) */
+                              for F16, the power of two nearest prod(h)/(dt^2 v_max^2)
+                              (the difference storages scale both fields alike) */
     int vp_padded;         /* 0: vp given on the physical grid, layer filled by edge
                               replication; 1: vp given on the padded grid */
     int max_src;           /* capacity of the source table (points), 0 selects 64 */

@@ -22,7 +22,8 @@ from ._lib import FDError  # noqa: F401
 
 __all__ = ["Grid", "Server", "FDError", "modeling", "diffusion", "build"]
 
-_STORAGE = {"f32": _lib.FD_STORE_F32, "f16": _lib.FD_STORE_F16, "bf16": _lib.FD_STORE_BF16}
+_STORAGE = {"f32": _lib.FD_STORE_F32, "f16": _lib.FD_STORE_F16, "bf16": _lib.FD_STORE_BF16,
+            "f16_diff": _lib.FD_STORE_F16_DIFF, "bf16_diff": _lib.FD_STORE_BF16_DIFF}
 
 
 def build() -> str:
@@ -50,7 +51,11 @@ def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
 
 class Grid:
     """A grid with its medium, owning a torch-allocated device workspace
-    that libfd borrows (fd_grid_create / fd_grid_destroy)."""
+    that libfd borrows (fd_grid_create / fd_grid_destroy).
+
+    storage: "f32", "f16", "bf16" (two 16-bit time levels), or, in 3D,
+    "f16_diff" / "bf16_diff" (the level and its difference from the
+    previous one, both 16-bit)."""
 
     def __init__(self, shape, spacing, vp: torch.Tensor, space_order: int = 8, nbl: int = 0,
                  origin=None, damp_max: float = 0.0, storage: str = "f32", amp_scale: float = 0.0,

@@ -21,6 +21,8 @@ FD_ERR_TIMEOUT = -6
 FD_STORE_F32 = 0
 FD_STORE_F16 = 1
 FD_STORE_BF16 = 2
+FD_STORE_F16_DIFF = 3
+FD_STORE_BF16_DIFF = 4
 
 FD_GRAD_RESIDUAL_GIVEN = 1
 FD_GRAD_BINOMIAL = 2

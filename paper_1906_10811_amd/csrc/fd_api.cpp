@@ -106,7 +106,9 @@ bool fdi_check_desc(const fd_grid_desc *d) {
     if (d->space_order < 2 || d->space_order > 2 * kMaxR || d->space_order % 2)
         return fdi_fail(FD_ERR_ARG, "space_order must be even, 2..16"), false;
     if (d->nbl < 0) return fdi_fail(FD_ERR_ARG, "nbl < 0"), false;
-    if (d->storage < 0 || d->storage > 2) return fdi_fail(FD_ERR_ARG, "storage"), false;
+    if (d->storage < 0 || d->storage > 4) return fdi_fail(FD_ERR_ARG, "storage"), false;
+    if ((d->storage == FD_STORE_F16_DIFF || d->storage == FD_STORE_BF16_DIFF) && d->ndim != 3)
+        return fdi_fail(FD_ERR_ARG, "the difference storages are 3D only"), false;
     if (d->amp_scale < 0.f || !std::isfinite(d->amp_scale)) return fdi_fail(FD_ERR_ARG, "amp_scale"), false;
     if (d->max_src < 0 || d->max_rec < 0 || d->zchunk < 0) return fdi_fail(FD_ERR_ARG, "capacities"), false;
     if (d->tile_x != 0 && d->tile_x != 32 && d->tile_x != 64 && d->tile_x != 96)
@@ -219,6 +221,16 @@ bool t2_enabled(const fd_grid_desc *d) {
     return d->time_block == 2 && d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR;
 }
 
+// 16-bit value-and-difference storage, and the element type of a storage.
+inline bool diff_storage(const fd_grid_desc *d) {
+    return d->storage == FD_STORE_F16_DIFF || d->storage == FD_STORE_BF16_DIFF;
+}
+inline Store elem_store(int storage) {
+    return storage == FD_STORE_F32 ? Store::F32
+           : (storage == FD_STORE_F16 || storage == FD_STORE_F16_DIFF) ? Store::F16
+                                                                        : Store::BF16;
+}
+
 // Tiles of the two-level step: 64 x 16 whatever the one-step shape.
 inline int t2_ntx(const Layout &L) { return (L.nx + 63) / 64; }
 inline int t2_nty(const Layout &L) { return (L.ny + 15) / 16; }
@@ -276,7 +288,7 @@ WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     w.uA = o; o += w.field_bytes;
     w.uB = o; o += w.field_bytes;
     const bool t2 = t2_enabled(d);
-    w.uC = o; if (t2) o += w.field_bytes;
+    w.uC = o; if (t2 || diff_storage(d)) o += w.field_bytes;   // (the difference field)
     w.uD = o; if (t2) o += w.field_bytes;
     w.damp = o; o = align_up(o + sizeof(float) * (size_t)(L.nx + L.ny + L.nz), 256);
     w.misc = o; o = align_up(o + sizeof(double) * kNPart + 256, 256);
@@ -345,6 +357,7 @@ struct fd_grid {
     // two-level step
     bool t2;
     void *uC, *uD;
+    bool diff;               // 16-bit value and difference: the difference lives in uC
     int t2_ntz, t2_zchunk;
     int *t2_pp;
     int4 *t2_corner;
@@ -745,9 +758,10 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     g->d = *desc;
     HIPCHK(hipGetDevice(&g->device));
     g->L = L;
-    g->st = (Store)desc->storage;
+    g->st = elem_store(desc->storage);
+    g->diff = diff_storage(desc);
     g->amp = (desc->storage != FD_STORE_F32 && desc->amp_scale > 0.f) ? desc->amp_scale : 1.f;
-    g->auto_amp = desc->storage == FD_STORE_F16 && !(desc->amp_scale > 0.f);
+    g->auto_amp = g->st == Store::F16 && !(desc->amp_scale > 0.f);
     g->nc = sparse_nodes(desc);
     fdi_second_derivative_weights(L.r, g->c);
     g->cell = 1.0;
@@ -832,7 +846,9 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
                 cus <= 0)
                 cus = 256;
-            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, m, g->shape3));
+            // (the forward slot runs the difference step under the difference storages)
+            const int mk = (m == kPlain && g->diff) ? (int)kDiff : m;
+            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, mk, g->shape3));
             const int tiles = std::max(1, g->ntx * g->nty + g->nstrip);
             const int kmax = std::min(occ, 3), prefer = g->st == Store::F32 ? 2 : 3;
             int nzc = 1;
@@ -879,7 +895,7 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     hipError_t e = hipSuccess;
     if ((e = launch_zero_field(L, g->uA, g->st, s)) != hipSuccess ||
         (e = launch_zero_field(L, g->uB, g->st, s)) != hipSuccess ||
-        (g->t2 && (e = launch_zero_field(L, g->uC, g->st, s)) != hipSuccess) ||
+        ((g->t2 || g->diff) && (e = launch_zero_field(L, g->uC, g->st, s)) != hipSuccess) ||
         (g->t2 && (e = launch_zero_field(L, g->uD, g->st, s)) != hipSuccess) ||
         (e = launch_zero_field(L, g->vel, Store::F32, s)) != hipSuccess ||
         (e = launch_zero_field(L, g->p, Store::F32, s)) != hipSuccess)
@@ -1019,12 +1035,13 @@ int fdi_forward_steps(fd_grid *g, const fd_shot *sh, int nt, int n0, int n1, flo
             HIPCHK(launch_sample(sm, g->prev, g->st, s));
         }
         a.u = g->cur;
-        a.prev = g->prev;
+        a.prev = g->diff ? g->uC : g->prev;   // the difference, or u^{n-1}
         a.out = g->prev;
+        a.out2 = g->diff ? g->uC : nullptr;   // the new difference, in place
         a.inj = make_inject(g, 0, sh->src_wavelet + (size_t)n * sh->nsrc, inj_scale);
         a.smp = make_sample(g, 1, sh->nrec, row(n - 1), smp_scale);
         a.nsamp_blocks = samp_blocks(a.smp);
-        HIPCHK(launch_step(a, g->st, kPlain, s));
+        HIPCHK(launch_step(a, g->st, g->diff ? kDiff : kPlain, s));
         g->rows_done = std::max(g->rows_done, std::min(n, nt));
         std::swap(g->cur, g->prev);
         ++n;
@@ -1060,6 +1077,7 @@ int fdi_forward_prepare(fd_grid *g, const fd_shot *sh, int nt, double dt, hipStr
 int fdi_forward_zero_state(fd_grid *g, hipStream_t s) {
     HIPCHK(launch_zero_field(g->L, g->uA, g->st, s));
     HIPCHK(launch_zero_field(g->L, g->uB, g->st, s));
+    if (g->diff) HIPCHK(launch_zero_field(g->L, g->uC, g->st, s));
     g->cur = g->uA;
     g->prev = g->uB;
     g->rows_done = 0;
@@ -1080,15 +1098,25 @@ extern "C" int fd_forward(fd_grid *g, const fd_shot *sh, int nt, double dt, floa
     const Layout &L = g->L;
     if (opts && opts->u0) HIPCHK(launch_dense_to_field(L, opts->u0, g->uA, g->st, g->amp, s));
     else HIPCHK(launch_zero_field(L, g->uA, g->st, s));
-    if (opts && opts->u_prev) HIPCHK(launch_dense_to_field(L, opts->u_prev, g->uB, g->st, g->amp, s));
+    if (opts && opts->u_prev && !g->diff) HIPCHK(launch_dense_to_field(L, opts->u_prev, g->uB, g->st, g->amp, s));
     else HIPCHK(launch_zero_field(L, g->uB, g->st, s));
+    if (g->diff) {   // the difference u^0 - u^{-1}, rounded once
+        if (opts && (opts->u0 || opts->u_prev))
+            HIPCHK(launch_dense_diff_to_field(L, opts->u0, opts->u_prev, g->uC, g->st, g->amp, s));
+        else
+            HIPCHK(launch_zero_field(L, g->uC, g->st, s));
+    }
     g->cur = g->uA;
     g->prev = g->uB;
     g->rows_done = 0;
     if ((rc = fdi_forward_steps(g, sh, nt, 0, nt, rec_out, nullptr, 1, s))) return rc;
     if (opts && opts->save_u) HIPCHK(launch_field_to_dense(L, g->cur, opts->save_u, g->st, 1.f / g->amp, s));
-    if (opts && opts->save_u_prev)
-        HIPCHK(launch_field_to_dense(L, g->prev, opts->save_u_prev, g->st, 1.f / g->amp, s));
+    if (opts && opts->save_u_prev) {
+        if (g->diff)
+            HIPCHK(launch_field_diff_to_dense(L, g->cur, g->uC, opts->save_u_prev, g->st, 1.f / g->amp, s));
+        else
+            HIPCHK(launch_field_to_dense(L, g->prev, opts->save_u_prev, g->st, 1.f / g->amp, s));
+    }
     return FD_OK;
     API_GUARD_END
 }

@@ -103,7 +103,10 @@ struct Imaging {
     float *gpart;           // kImage: float32 partial sum, folded into float64 by the host loop
 };
 
-enum StepMode { kPlain = 0, kBracket = 1, kImage = 2 };
+// kDiff (16-bit 3D storage only): the grid keeps u^n and the difference
+// delta = u^n - u^{n-1}; `prev` is the difference field (read at the point),
+// `out` receives u^{n+1} and `out2` the new difference (in place of `prev`).
+enum StepMode { kPlain = 0, kBracket = 1, kImage = 2, kDiff = 3 };
 
 struct StepArgs {
     Layout L;
@@ -159,6 +162,12 @@ hipError_t launch_dense_to_field(const Layout &L, const float *dense, void *f, S
                                  float scale, hipStream_t s);
 hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, Store st,
                                  float scale, hipStream_t s);
+// Difference storage: d = round(scale * (a - b)) from two dense fields, and
+// dense = (u - d) / scale from the stored value and difference (16-bit).
+hipError_t launch_dense_diff_to_field(const Layout &L, const float *a, const float *b, void *d, Store st,
+                                      float scale, hipStream_t s);
+hipError_t launch_field_diff_to_dense(const Layout &L, const void *u, const void *d, float *dense, Store st,
+                                      float scale, hipStream_t s);
 // One explicit diffusion step, 2D: out = u + w0 u + sum_j wx_j (..) + wz_j (..)
 // (weights already multiplied by nu dt).
 hipError_t launch_diffuse2d(const Layout &L, const float *u, float *out, float w0, const float *wx,

@@ -201,6 +201,15 @@ __device__ inline float update_point(float c, float m, float p, float lap, float
     return alpha * __builtin_fmaf(p, lap + src, t);
 }
 
+// The same update for the difference storage: with u^{n-1} = u^n - d,
+// u^{n+1} - u^n = [(1 - s) d + p (lap + src)] / (1 + s), computed directly
+// (no cancellation of the two levels).
+__device__ inline float update_diff(float d, float p, float lap, float src, float s) {
+    const float alpha = (s == 0.f) ? 1.f : __builtin_amdgcn_rcpf(1.f + s);
+    const float beta = 1.f - s;
+    return alpha * __builtin_fmaf(p, lap + src, beta * d);
+}
+
 // One radius-j term of the 2D Laplacian at a point: the weights times the
 // sums of the two neighbours at distance j along each axis.
 __device__ inline float lap_term2(float wx, float xs, float wz, float zs) {
@@ -495,10 +504,29 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
             const float src[4] = {src4.x, src4.y, src4.z, src4.w};
             const float sz = s_dz[z - z0];
             float un[4];
+            [[maybe_unused]] typename E::Raw draw;   // kDiff: the new difference as stored
+            if constexpr (MODE == kDiff) {
+                // value and difference: mvf is d = u^n - u^{n-1}; the new
+                // difference is rounded to 16 bits first, and u^{n+1} is u^n
+                // plus that stored difference, so the stored pair stays
+                // consistent
+                static_assert(S != Store::F32, "difference storage is 16-bit");
+                float4 d4;
+                d4.x = update_diff(mvf.x, cur.pv.x, lap[0], src[0], sxy[0] + sz);
+                d4.y = update_diff(mvf.y, cur.pv.y, lap[1], src[1], sxy[1] + sz);
+                d4.z = update_diff(mvf.z, cur.pv.z, lap[2], src[2], sxy[2] + sz);
+                d4.w = update_diff(mvf.w, cur.pv.w, lap[3], src[3], sxy[3] + sz);
+                asm volatile("" : "+v"(d4.x), "+v"(d4.y), "+v"(d4.z), "+v"(d4.w));
+                draw = E::pack(d4);
+                const float4 ds = E::cvt(draw);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                un[i] = update_point(comp(QQ(R), i), comp(mvf, i), comp(cur.pv, i), lap[i], src[i],
-                                     sxy[i] + sz);
+                for (int i = 0; i < 4; ++i) un[i] = comp(QQ(R), i) + comp(ds, i);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    un[i] = update_point(comp(QQ(R), i), comp(mvf, i), comp(cur.pv, i), lap[i], src[i],
+                                         sxy[i] + sz);
+            }
             const long long off = base + (long long)z * plane;
             float4 r4 = make_float4(un[0], un[1], un[2], un[3]);
             // All four results are computed here, before the ragged-edge
@@ -526,6 +554,21 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
                     if (i < nvalid) E::st(O + off + i, rv[i]);
+            }
+            if constexpr (MODE == kDiff) {
+                T *D = (T *)a.out2;
+                if (nvalid >= 4) {
+                    if (a.out_cached)
+                        *reinterpret_cast<typename E::Raw *>(D + off) = draw;
+                    else
+                        st2nt_u32(D + off, draw);
+                } else {
+                    const float4 ds = E::cvt(draw);
+                    const float dv[3] = {ds.x, ds.y, ds.z};
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        if (i < nvalid) E::st(D + off + i, dv[i]);
+                }
             }
             if constexpr (MODE == kBracket) {
                 float sv[4];
@@ -1469,10 +1512,17 @@ StepFn pick(int ndim, int r, int tw4) {
     return ndim == 3 ? Tb::get3(r, tw4) : Tb::get2(r);
 }
 
-// The gradient modes exist for float32 storage only.
+// The gradient modes exist for float32 storage only, the difference
+// storage for 16-bit 3D fields only.
 StepFn pick_step(int ndim, int r, Store st, int mode, int tw4) {
     if (mode == kBracket) return st == Store::F32 ? pick<Store::F32, kBracket>(ndim, r, tw4) : nullptr;
     if (mode == kImage) return st == Store::F32 ? pick<Store::F32, kImage>(ndim, r, tw4) : nullptr;
+    if (mode == kDiff) {
+        if (ndim != 3) return nullptr;
+        if (st == Store::F16) return Table<Store::F16, kDiff, 1, 2, 3, 4, 5, 6, 7, 8>::get3(r, tw4);
+        if (st == Store::BF16) return Table<Store::BF16, kDiff, 1, 2, 3, 4, 5, 6, 7, 8>::get3(r, tw4);
+        return nullptr;
+    }
     switch (st) {
         case Store::F32: return pick<Store::F32, kPlain>(ndim, r, tw4);
         case Store::F16: return pick<Store::F16, kPlain>(ndim, r, tw4);
@@ -1633,6 +1683,61 @@ hipError_t launch_field_to_dense(const Layout &L, const void *f, float *dense, S
         case Store::F16: hipLaunchKernelGGL(k_field_to_dense<Store::F16>, g, b, 0, s, L, f, dense, scale); break;
         case Store::BF16: hipLaunchKernelGGL(k_field_to_dense<Store::BF16>, g, b, 0, s, L, f, dense, scale); break;
     }
+    return hipGetLastError();
+}
+
+namespace {
+template <Store S>
+__global__ void k_dense_diff_to_field(const Layout L, const float *a, const float *b, void *d, float scale) {
+    using E = Elem<S>;
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        E::st((typename E::T *)d + L.offset(x, y, z), ((a ? a[i] : 0.f) - (b ? b[i] : 0.f)) * scale);
+    }
+}
+
+template <Store S>
+__global__ void k_field_diff_to_dense(const Layout L, const void *u, const void *d, float *dense, float scale) {
+    using E = Elem<S>;
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        const long long o = L.offset(x, y, z);
+        dense[i] = (E::ld((const typename E::T *)u + o) - E::ld((const typename E::T *)d + o)) * scale;
+    }
+}
+}  // namespace
+
+hipError_t launch_dense_diff_to_field(const Layout &L, const float *a, const float *b, void *d, Store st,
+                                      float scale, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    const dim3 g(grid_for(n)), bl(kBlock);
+    if (st == Store::F16)
+        hipLaunchKernelGGL(k_dense_diff_to_field<Store::F16>, g, bl, 0, s, L, a, b, d, scale);
+    else if (st == Store::BF16)
+        hipLaunchKernelGGL(k_dense_diff_to_field<Store::BF16>, g, bl, 0, s, L, a, b, d, scale);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_field_diff_to_dense(const Layout &L, const void *u, const void *d, float *dense, Store st,
+                                      float scale, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    const dim3 g(grid_for(n)), bl(kBlock);
+    if (st == Store::F16)
+        hipLaunchKernelGGL(k_field_diff_to_dense<Store::F16>, g, bl, 0, s, L, u, d, dense, scale);
+    else if (st == Store::BF16)
+        hipLaunchKernelGGL(k_field_diff_to_dense<Store::BF16>, g, bl, 0, s, L, u, d, dense, scale);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

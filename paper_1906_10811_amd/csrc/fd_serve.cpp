@@ -440,8 +440,7 @@ extern "C" int fd_submit(fd_server *srv, const fd_request *req, uint64_t *ticket
     try {
         if (!srv || !req || !ticket) return fdi_fail(FD_ERR_ARG, "null argument");
         if (!fdi_check_desc(&req->grid)) return FD_ERR_ARG;
-        if (req->grid.storage != FD_STORE_F32 && req->grid.storage != FD_STORE_F16 &&
-            req->grid.storage != FD_STORE_BF16)
+        if (req->grid.storage < FD_STORE_F32 || req->grid.storage > FD_STORE_BF16_DIFF)
             return fdi_fail(FD_ERR_ARG, "storage");
         if (req->nt < 1 || req->nsrc < 1 || req->nrec < 1 || !req->vp_host || !req->src_xyz ||
             !req->rec_xyz || !req->wavelet_host || !req->rec_out_host || !(req->dt > 0.0))

@@ -71,6 +71,9 @@ def test_workspace_bytes_grow_with_grid(lib):
     rc6, b6 = _bytes(lib, _desc(shape=(64, 48, 32), time_block=2))
     assert rc5 == 0 and rc6 == 0 and b5 == b1
     assert b6 - b5 >= 2 * 4 * (84 * 68 * 52)
+    # value-and-difference storage keeps a third 16-bit field
+    rc9, b9 = _bytes(lib, _desc(shape=(64, 48, 32), storage=_lib.FD_STORE_BF16_DIFF))
+    assert rc9 == 0 and b9 - b3 >= 2 * (84 * 68 * 52) and b9 < b1
     rc7, b7 = _bytes(lib, _desc(shape=(64, 48, 32), so=10))
     rc8, b8 = _bytes(lib, _desc(shape=(64, 48, 32), so=10, time_block=1))
     assert rc7 == 0 and b7 == b8
@@ -80,7 +83,8 @@ def test_workspace_bytes_grow_with_grid(lib):
     dict(ndim=4), dict(so=3), dict(so=18), dict(so=0), dict(nbl=-1), dict(shape=(1, 8, 8)),
     dict(storage=7), dict(tile_x=48), dict(tile_x=-32), dict(tile_x=128),
     dict(time_block=3), dict(time_block=-1), dict(time_block=2, storage=2), dict(time_block=2, so=10),
-    dict(time_block=2, ndim=2),
+    dict(time_block=2, ndim=2), dict(storage=3, ndim=2), dict(storage=4, ndim=2), dict(storage=5),
+    dict(time_block=2, storage=4),
 ])
 def test_invalid_descriptors_rejected(lib, bad):
     rc, _ = _bytes(lib, _desc(**bad))

@@ -29,7 +29,7 @@ def _shapes(c, shapes=(64, 32, 96), **kw):
     return out
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f16_diff", "bf16_diff"])
 @pytest.mark.parametrize("so", [4, 8, 16])
 def test_forward_bitwise_across_tile_shapes(storage, so):
     """80 x 70 x 33 + 6 (92 x 82 x 45 padded): ragged last tiles in x and y
