@@ -142,6 +142,21 @@ def copy_probe(torch, dev, stream, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / secs / 1e9
 
 
+def counter_references(torch, dev, stream, nbytes=1 << 30):
+    """Untimed elementwise kernels of known size, so that a rocprofv3 counter
+    run of this script scales FETCH_SIZE / WRITE_SIZE by kernels whose lane
+    accesses match the step's: a float32 multiply (16 bytes per lane and
+    access) and a float16 one (8 bytes), each reading and writing nbytes."""
+    with torch.cuda.stream(stream):
+        for dt in (torch.float32, torch.float16):
+            n = nbytes // (4 if dt == torch.float32 else 2)
+            a = torch.ones(n, dtype=dt, device=dev)
+            b = torch.empty_like(a)
+            torch.mul(a, 1.0, out=b)
+            torch.cuda.synchronize()
+            del a, b
+
+
 def _oracle_setup(w, v):
     import oracle
     og = oracle.Grid(tuple(w["shape"]), tuple(w["spacing"]), tuple(w["origin"]), w["space_order"], w["nbl"])
@@ -537,6 +552,7 @@ def main():
 
     copy_gbs = copy_probe(torch, dev, stream)
     log("stream copy: %.0f GB/s" % copy_gbs)
+    counter_references(torch, dev, stream)
     log("headline: layered3d_256 forward, steps=%d warmup=%d" % (args.steps, args.warmup))
     w, h = bench_headline(torch, dev, args.steps, args.warmup, stream)
     log("headline: %.1f Gpts/s, %.1f us per launch" % (h["gpts"], h["launch_us"]))
