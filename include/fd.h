@@ -255,9 +255,12 @@ typedef struct fd_ckpt_action {
 /*
  * Schedule reversing nt steps with `slots` snapshot slots besides the initial
  * state, minimising the number of forward steps (binomial checkpointing,
- * Griewank-Walther; split points found by dynamic programming).  Writes up
- * to `capacity` actions (actions may be NULL to query the count), the count
- * to *n_actions and the ADVANCE steps to *forward_steps (nullable).
+ * Griewank-Walther: the smallest optimal split of each segment, found by
+ * bisection on the closed-form cost; host time and memory grow with the
+ * number of actions only).  Writes up to `capacity` actions (actions may be
+ * NULL to query the count), the count to *n_actions and the ADVANCE steps to
+ * *forward_steps (nullable).  FD_ERR_ARG for nt < 1, slots < 0 or nt above
+ * INT_MAX / 8.
  */
 int fd_checkpoint_schedule(int nt, int slots, fd_ckpt_action *actions, int capacity,
                            int *n_actions, long long *forward_steps);

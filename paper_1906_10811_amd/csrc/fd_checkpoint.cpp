@@ -3,20 +3,27 @@
 //
 // To reverse nt time steps the adjoint needs, for n = nt-1 down to 0, the
 // state (u^n, u^{n-1}) from which one forward step gives u^{n+1} and the
-// imaging bracket of level n.  With `slots` snapshot slots besides the
-// initial state, the schedule minimising the number of forward steps is
-// built by dynamic programming over the split point of each segment:
+// imaging bracket of level n.  With c snapshot slots besides the initial
+// state, the fewest forward steps T(l, c) to reverse l steps satisfy
 //
-//   T(l, c) = 0                                   l = 1
-//   T(l, 0) = l (l - 1) / 2                       advance from the segment start each time
+//   T(1, c) = 0,   T(l, 0) = l (l - 1) / 2,
 //   T(l, c) = min_{1 <= m < l} m + T(l - m, c - 1) + T(m, c)
 //
-// i.e. advance m steps, store a snapshot, reverse the last l - m steps with
-// one slot fewer, then reverse the first m steps from the segment start with
-// the slot returned.  This is the optimal offline schedule whose cost the
-// binomial checkpointing theorem of Griewank and Walther gives in closed
-// form; the DP finds the split points directly instead of using their
-// placement rules.
+// (advance m steps, store a snapshot, reverse the last l - m steps with one
+// slot fewer, then the first m steps with the slot returned).  The binomial
+// checkpointing theorem of Griewank and Walther gives the minimum in closed
+// form: with s = c + 1 checkpoints (the initial state included) and r the
+// least integer with C(s + r, s) >= l,
+//
+//   T(l, c) = r l - C(s + r, s + 1),
+//
+// so T(l + 1, c) - T(l, c) = r(l + 1): T is convex in l, and so is the cost
+// of a split as a function of m.  The schedule takes the smallest optimal m
+// of each split, found by bisection on the sign of the cost's difference
+//
+//   D(m) = 1 + r_{s}(m + 1) - r_{s-1}(l - m),
+//
+// O(log l) evaluations of r per split instead of a table of all (l, c).
 #include <algorithm>
 #include <climits>
 #include <cstdint>
@@ -27,37 +34,39 @@
 
 namespace {
 
-struct Plan {
-    int nt, slots;
-    std::vector<long long> T;   // (nt+1) x (slots+1), forward steps
-    std::vector<int> M;         // argmin split
-    long long &t(int l, int c) { return T[(size_t)l * (slots + 1) + c]; }
-    int &m(int l, int c) { return M[(size_t)l * (slots + 1) + c]; }
-};
-
-void solve(Plan &p) {
-    p.T.assign((size_t)(p.nt + 1) * (p.slots + 1), 0);
-    p.M.assign((size_t)(p.nt + 1) * (p.slots + 1), 0);
-    for (int l = 1; l <= p.nt; ++l) {
-        p.t(l, 0) = (long long)l * (l - 1) / 2;
-        for (int c = 1; c <= p.slots; ++c) {
-            if (l == 1) {
-                p.t(l, c) = 0;
-                continue;
-            }
-            long long best = LLONG_MAX;
-            int arg = 1;
-            for (int mm = 1; mm < l; ++mm) {
-                const long long v = mm + p.t(l - mm, c - 1) + p.t(mm, c);
-                if (v < best) {
-                    best = v;
-                    arg = mm;
-                }
-            }
-            p.t(l, c) = best;
-            p.m(l, c) = arg;
-        }
+// r_s(n): the least r >= 0 with C(s + r, s) >= n (s >= 1, n >= 1)
+long long reps(long long n, int s) {
+    if (n <= 1) return 0;
+    if (s == 1) return n - 1;   // C(1 + r, 1) = r + 1
+    long long b = 1, r = 0;     // b = C(s + r, r)
+    while (b < n) {
+        b = b * (s + r + 1) / (r + 1);   // exact: C(s + r + 1, r + 1)
+        ++r;
     }
+    return r;
+}
+
+// T(l, c) in closed form
+long long fwd_steps(long long l, int c) {
+    if (l <= 1) return 0;
+    if (c == 0) return l * (l - 1) / 2;
+    const int s = c + 1;
+    const long long r = reps(l, s);
+    long long b = 1;   // C(s + r, s + 1) = C(s + r, r - 1)
+    for (long long k = 0; k < r - 1; ++k) b = b * (s + 2 + k) / (k + 1);
+    return r * l - (r >= 1 ? b : 0);
+}
+
+// smallest optimal split of (l, c), c >= 1, l >= 2
+int split(int l, int c) {
+    auto d = [&](int m) { return 1 + reps(m + 1, c + 1) - reps(l - m, c); };
+    int lo = 1, hi = l - 1;   // the answer is the first m in [1, l - 2] with D(m) >= 0, else l - 1
+    while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (d(mid) >= 0) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 struct Emitter {
@@ -88,7 +97,7 @@ struct Emitter {
 
 // Reverse steps [s, s + l) with the state of level s in slot `at` and
 // free slots `c`, whose indices are next_free .. next_free + c - 1.
-void emit(Plan &p, Emitter &e, int s, int l, int c, int at, int next_free) {
+void emit(Emitter &e, int s, int l, int c, int at, int next_free) {
     if (l == 1) {
         e.push(FD_ACT_RESTORE, s, 0, at);
         e.push(FD_ACT_YOUTURN, s, 1, -1);
@@ -102,28 +111,29 @@ void emit(Plan &p, Emitter &e, int s, int l, int c, int at, int next_free) {
         }
         return;
     }
-    const int mm = p.m(l, c);
+    const int mm = split(l, c);
     e.push(FD_ACT_RESTORE, s, 0, at);
     e.push(FD_ACT_ADVANCE, s, mm, -1);
     e.push(FD_ACT_STORE, s + mm, 0, next_free);
-    emit(p, e, s + mm, l - mm, c - 1, next_free, next_free + 1);
-    emit(p, e, s, mm, c, at, next_free);
+    emit(e, s + mm, l - mm, c - 1, next_free, next_free + 1);
+    emit(e, s, mm, c, at, next_free);
 }
 
 }  // namespace
 
 int fdi_checkpoint_plan(int nt, int slots, std::vector<fd_ckpt_action> *actions, long long *fwd) {
     if (nt < 1 || slots < 0) return fdi_fail(FD_ERR_ARG, "nt >= 1 and slots >= 0");
-    if ((long long)nt * nt * (slots + 1) > 4000000000LL)
-        return fdi_fail(FD_ERR_ARG, "schedule too large (nt %d, slots %d)", nt, slots);
-    Plan p{nt, std::min(slots, nt)};
-    solve(p);
+    // at most about four actions per time step (restore, advance, store,
+    // reverse), counted in an int
+    if (nt > INT_MAX / 8) return fdi_fail(FD_ERR_ARG, "schedule too large (nt %d)", nt);
+    const int c = std::min(slots, nt);
+    const long long total = fwd_steps(nt, c);
     Emitter cnt{nullptr, 0};
-    emit(p, cnt, 0, nt, p.slots, 0, 1);
+    emit(cnt, 0, nt, c, 0, 1);
     actions->resize(cnt.n);
     Emitter e{actions->data(), cnt.n};
-    emit(p, e, 0, nt, p.slots, 0, 1);
-    if (fwd) *fwd = p.t(nt, p.slots);
+    emit(e, 0, nt, c, 0, 1);
+    if (fwd) *fwd = total;
     return FD_OK;
 }
 

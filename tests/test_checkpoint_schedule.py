@@ -2,7 +2,10 @@
 schedule is executable and reverses the steps in order, each step is
 computed for the first time exactly once, and the number of forward steps
 equals the optimum -- the closed form of the binomial checkpointing theorem
-(Griewank and Walther) and an exhaustive search on small cases."""
+(Griewank and Walther) and an exhaustive search on small cases.  The split
+of each segment is the smallest optimal one of the exhaustive recurrence,
+and schedules far longer than a table over all (length, slots) pairs could
+hold are planned too."""
 import functools
 from math import comb
 
@@ -95,3 +98,23 @@ def test_more_slots_never_cost_more():
             assert fwd <= prev
         prev = fwd
     assert prev < 3 * 300
+
+
+def test_first_split_is_the_smallest_optimal_one():
+    """The first snapshot of a schedule is taken after the smallest m that
+    minimises m + T(l - m, c - 1) + T(m, c) (exhaustive recurrence)."""
+    for l in range(2, 40):
+        for c in range(1, 6):
+            acts, _ = _lib.checkpoint_schedule(l, c)
+            cc = min(c, l)
+            costs = [m + brute(l - m, cc - 1) + brute(m, cc) for m in range(1, l)]
+            want = 1 + costs.index(min(costs))
+            assert acts[0][0] == RES and acts[1][0] == ADV and acts[2][0] == STO, (l, c)
+            assert acts[1][2] == want and acts[2][1] == want, (l, c, acts[1], want)
+
+
+@pytest.mark.parametrize("nt,slots", [(20000, 30), (100000, 50)])
+def test_long_schedules(nt, slots):
+    acts, fwd = _lib.checkpoint_schedule(nt, slots)
+    assert fwd == closed_form(nt, slots)
+    assert simulate(nt, slots, acts) == fwd
