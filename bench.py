@@ -469,7 +469,7 @@ def bench_diffusion(torch, dev, stream):
     """The thesis's own benchmark (Section 5.1.2): 2D diffusion, nu = 0.5,
     first order in time, FP32, 1000 steps, grids 2500^2 and 10000^2, space
     orders 2..12.  Algorithmic bytes: read u^n, write u^{n+1} = 8 B/point."""
-    from paper_1906_10811_amd import diffusion
+    from paper_1906_10811_amd import diffusion, diffusion_dt_limit
     out = {}
     for n in (2500, 10000):
         h = 1.0 / (n - 1)
@@ -478,11 +478,7 @@ def bench_diffusion(torch, dev, stream):
         res = torch.empty_like(u0)
         for so in (2, 4, 8, 12):
             r = so // 2
-            c = [0.0] * (r + 1)
-            for j in range(1, r + 1):
-                c[j] = 2 * (-1) ** (j + 1) * math.factorial(r) ** 2 / (j * j * math.factorial(r - j) * math.factorial(r + j))
-            s_odd = sum(c[j] for j in range(1, r + 1, 2))
-            dt = 0.8 / (2.0 * s_odd * 2.0 / h ** 2) / 0.5
+            dt = 0.8 * diffusion_dt_limit((n, n), (h, h), so, 0.5)
             diffusion(u0, (h, h), so, 0.5, dt, 10, out=res, stream=stream, time_block=1)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)

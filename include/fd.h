@@ -387,6 +387,13 @@ typedef struct fd_diffusion_desc {
 /* Device workspace for fd_diffusion_run (two pitched float32 fields). */
 int fd_diffusion_workspace_bytes(const fd_diffusion_desc *desc, size_t *bytes);
 
+/* The largest stable time step of the explicit scheme (Section 5.1.2's
+ * update u^{n+1} = u^n + nu dt Lap_h u^n): *dt_max = 1 / (2 nu sum_{j odd}
+ * c_j sum_a h_a^-2), c_j the maximal-order second-derivative weights of the
+ * descriptor's space order; fd_diffusion_run refuses nu dt above nu dt_max.
+ * Host only.  FD_ERR_ARG for an invalid descriptor or a null output. */
+int fd_diffusion_dt_limit(const fd_diffusion_desc *desc, double *dt_max);
+
 /*
  * nt explicit steps from u0_dev (device float32, dense [Ny][Nx]) into
  * u_out_dev (device float32, dense, may alias u0_dev).  workspace: >= the

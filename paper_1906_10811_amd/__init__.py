@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import FDError  # noqa: F401
 
-__all__ = ["Grid", "Server", "FDError", "modeling", "diffusion", "build"]
+__all__ = ["Grid", "Server", "FDError", "modeling", "diffusion", "diffusion_dt_limit", "build"]
 
 _STORAGE = {"f32": _lib.FD_STORE_F32, "f16": _lib.FD_STORE_F16, "bf16": _lib.FD_STORE_BF16,
             "f16_diff": _lib.FD_STORE_F16_DIFF, "bf16_diff": _lib.FD_STORE_BF16_DIFF}
@@ -388,6 +388,19 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def diffusion_dt_limit(shape, spacing, space_order: int, nu: float) -> float:
+    """fd_diffusion_dt_limit: the largest stable dt of the explicit scheme on
+    an [Ny, Nx] = reversed(shape) grid (host only)."""
+    d = _lib.DiffusionDesc()
+    d.shape[0], d.shape[1] = int(shape[0]), int(shape[1])
+    d.spacing[0], d.spacing[1] = float(spacing[0]), float(spacing[1])
+    d.space_order = int(space_order)
+    d.nu = float(nu)
+    out = ctypes.c_double()
+    _lib.check(_lib.load().fd_diffusion_dt_limit(ctypes.byref(d), ctypes.byref(out)))
+    return out.value
 
 
 def diffusion(u0: torch.Tensor, spacing, space_order: int, nu: float, dt: float, nt: int,

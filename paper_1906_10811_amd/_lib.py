@@ -39,7 +39,7 @@ EXPORTS = (
     "fd_forward", "fd_adjoint", "fd_gradient_workspace_bytes", "fd_gradient",
     "fd_server_create", "fd_submit", "fd_wait", "fd_request_bytes", "fd_server_stats",
     "fd_server_destroy", "fd_last_error", "fd_diffusion_workspace_bytes", "fd_diffusion_run",
-    "fd_checkpoint_schedule", "fd_diffusion_run_noalloc",
+    "fd_checkpoint_schedule", "fd_diffusion_run_noalloc", "fd_diffusion_dt_limit",
 )
 
 
@@ -194,6 +194,7 @@ def load() -> ctypes.CDLL:
         "fd_diffusion_workspace_bytes": (I, [ctypes.POINTER(DiffusionDesc), PS]),
         "fd_diffusion_run": (I, [ctypes.POINTER(DiffusionDesc), P, S, P, P, I, D, P]),
         "fd_diffusion_run_noalloc": (I, [ctypes.POINTER(DiffusionDesc), P, P, I, D, P]),
+        "fd_diffusion_dt_limit": (I, [ctypes.POINTER(DiffusionDesc), ctypes.POINTER(D)]),
         "fd_checkpoint_schedule": (I, [I, I, ctypes.POINTER(CkptAction), I, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_longlong)]),
     }

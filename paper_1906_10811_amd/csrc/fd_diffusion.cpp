@@ -34,7 +34,25 @@ bool to_grid_desc(const fd_diffusion_desc *d, fd_grid_desc *g) {
     return fdi_check_desc(g);
 }
 
+// nu dt above this is unstable: 1 / (2 sum_{j odd} c_j (hx^-2 + hy^-2))
+double nu_dt_limit(const fd_diffusion_desc *d, int r) {
+    double c[kMaxR + 1];
+    fdi_second_derivative_weights(r, c);
+    double s_odd = 0.0;
+    for (int j = 1; j <= r; j += 2) s_odd += c[j];
+    const double hx2 = d->spacing[0] * d->spacing[0], hy2 = d->spacing[1] * d->spacing[1];
+    return 1.0 / (2.0 * s_odd * (1.0 / hx2 + 1.0 / hy2));
+}
+
 }  // namespace
+
+extern "C" int fd_diffusion_dt_limit(const fd_diffusion_desc *desc, double *dt_max) {
+    fd_grid_desc g;
+    if (!dt_max) return fdi_fail(FD_ERR_ARG, "null output");
+    if (!to_grid_desc(desc, &g)) return FD_ERR_ARG;
+    *dt_max = nu_dt_limit(desc, desc->space_order / 2) / desc->nu;
+    return FD_OK;
+}
 
 extern "C" int fd_diffusion_workspace_bytes(const fd_diffusion_desc *desc, size_t *bytes) {
     fd_grid_desc g;
@@ -58,10 +76,8 @@ int run_diffusion(const fd_diffusion_desc *desc, void *workspace, size_t ws_byte
     if (ws_bytes < 2 * fb) return fdi_fail(FD_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, 2 * fb);
     double c[kMaxR + 1];
     fdi_second_derivative_weights(L.r, c);
-    double s_odd = 0.0;
-    for (int j = 1; j <= L.r; j += 2) s_odd += c[j];
     const double hx2 = desc->spacing[0] * desc->spacing[0], hy2 = desc->spacing[1] * desc->spacing[1];
-    const double limit = 1.0 / (2.0 * s_odd * (1.0 / hx2 + 1.0 / hy2));
+    const double limit = nu_dt_limit(desc, L.r);
     if (desc->nu * dt > limit)
         return fdi_fail(FD_ERR_UNSTABLE, "nu dt %.6g exceeds the explicit limit %.6g", desc->nu * dt, limit);
     hipStream_t s = (hipStream_t)stream;

@@ -106,3 +106,26 @@ def test_request_bytes(lib):
     assert lib.fd_request_bytes(ctypes.byref(r), ctypes.byref(n)) == 0
     _, gb = _bytes(lib, _desc(shape=(32, 32, 32), nbl=8))
     assert n.value >= gb + 4 * 32 ** 3 + 4 * 100 * 17
+
+
+def test_diffusion_dt_limit_is_the_von_neumann_bound(lib):
+    """fd_diffusion_dt_limit against the stability bound of forward Euler:
+    dt_max = 2 / (nu max_theta S), S the symbol of the 2D stencil built from
+    the oracle's weights, maximised on a fine grid of wavenumbers; so 2 and
+    equal spacing give the textbook h^2 / (4 nu)."""
+    import numpy as np
+    import oracle
+    from paper_1906_10811_amd import diffusion_dt_limit
+    th = np.linspace(0.0, np.pi, 20001)
+    for so in (2, 4, 8, 12, 16):
+        c = oracle.fd_weights(so)
+        sym = -(c[0] + 2.0 * sum(c[j] * np.cos(j * th) for j in range(1, so // 2 + 1)))
+        for hx, hy, nu in ((0.1, 0.1, 0.5), (2.0, 3.0, 1.7)):
+            want = 2.0 / (nu * sym.max() * (1.0 / hx ** 2 + 1.0 / hy ** 2))
+            got = diffusion_dt_limit((50, 40), (hx, hy), so, nu)
+            assert abs(got - want) <= 1e-9 * want, (so, got, want)
+    assert abs(diffusion_dt_limit((9, 9), (0.5, 0.5), 2, 2.0) - 0.5 ** 2 / 8.0) < 1e-15
+    d = _lib.DiffusionDesc()
+    assert lib.fd_diffusion_dt_limit(ctypes.byref(d), None) == _lib.FD_ERR_ARG
+    out = ctypes.c_double()
+    assert lib.fd_diffusion_dt_limit(ctypes.byref(d), ctypes.byref(out)) == _lib.FD_ERR_ARG   # zero shape
