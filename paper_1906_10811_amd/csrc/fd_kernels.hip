@@ -194,20 +194,24 @@ __device__ inline void gather_sources(const Inject &inj, int e0, int e1, int x, 
 // so that every kernel instantiation (plain, bracket, imaging; any storage)
 // rounds them identically: a state recomputed by one step mode is bitwise
 // the state another mode computed, which checkpoint recomputation relies on.
+//
+// With alpha = 1/(1+s) and (1-s)/(1+s) = 2 alpha - 1 the centred update
+// alpha [2c - (1-s) m + p (lap + src)] is m + alpha [2 (c - m) + p (lap + src)]:
+// no beta, and c - m is exact where the two levels are close.  The hardware
+// reciprocal of 1 is exactly 1 (checked, as for every power of two), so
+// outside the damping layer alpha is 1 with no select.
 __device__ inline float update_point(float c, float m, float p, float lap, float src, float s) {
-    const float alpha = (s == 0.f) ? 1.f : __builtin_amdgcn_rcpf(1.f + s);
-    const float beta = 1.f - s;
-    const float t = __builtin_fmaf(-beta, m, 2.f * c);
-    return alpha * __builtin_fmaf(p, lap + src, t);
+    const float alpha = __builtin_amdgcn_rcpf(1.f + s);
+    return __builtin_fmaf(alpha, __builtin_fmaf(p, lap + src, 2.f * (c - m)), m);
 }
 
 // The same update for the difference storage: with u^{n-1} = u^n - d,
-// u^{n+1} - u^n = [(1 - s) d + p (lap + src)] / (1 + s), computed directly
-// (no cancellation of the two levels).
+// u^{n+1} - u^n = [(1 - s) d + p (lap + src)] / (1 + s)
+//               = alpha [2 d + p (lap + src)] - d,
+// computed directly (no cancellation of the two levels).
 __device__ inline float update_diff(float d, float p, float lap, float src, float s) {
-    const float alpha = (s == 0.f) ? 1.f : __builtin_amdgcn_rcpf(1.f + s);
-    const float beta = 1.f - s;
-    return alpha * __builtin_fmaf(p, lap + src, beta * d);
+    const float alpha = __builtin_amdgcn_rcpf(1.f + s);
+    return __builtin_fmaf(alpha, __builtin_fmaf(p, lap + src, 2.f * d), -d);
 }
 
 // One radius-j term of the 2D Laplacian at a point: the weights times the
