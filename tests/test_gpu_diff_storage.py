@@ -128,3 +128,38 @@ def test_difference_storage_through_the_server_and_rejections():
         assert info["status"] == 0
         assert np.array_equal(out, alone[st]), st
     srv.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_adjoint_on_a_difference_grid_is_the_two_level_adjoint(storage):
+    """fd_adjoint keeps two 16-bit levels whatever the forward storage, so on
+    a difference-storage grid it is bitwise the adjoint of the two-level grid
+    of the same type."""
+    need_gpu()
+    c = case((50, 40, 30), 8, 5, 40, seed=23, nsrc=2, nrec=8)
+    dev = torch.device("cuda:0")
+    res = torch.from_numpy(np.random.default_rng(2).standard_normal((c["nt"], len(c["rec"]))).astype(np.float32)).to(dev)
+    out = []
+    for st in (storage, storage + "_diff"):
+        g = gpu_grid(c, storage=st)
+        out.append(g.adjoint(c["src"], c["rec"], res, c["dt"]))
+        torch.cuda.synchronize()
+        g.close()
+    assert torch.equal(out[0], out[1])
+
+
+def test_difference_storage_with_windowed_sinc_points():
+    """Kaiser-windowed sinc sources and receivers (half-width 3, 216 nodes)
+    with value-and-difference storage, against the FP64 oracle at the
+    storage bars."""
+    need_gpu()
+    c = case((60, 50, 40), 8, 6, 60, seed=29, nsrc=2, nrec=9)
+    c["sinc"] = 3
+    want, *_ = oracle_forward(c)
+    for st, bar in (("f16_diff", 1e-3), ("bf16_diff", 1e-2)):
+        g = gpu_grid(c, storage=st)
+        _, rec = gpu_forward(c, grid=g)
+        e = rel_l2(rec.cpu().numpy(), want)
+        print("%s sinc 3 vs FP64: %.3e" % (st, e), flush=True)
+        assert e <= bar, (st, e)
+        g.close()
