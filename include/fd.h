@@ -124,10 +124,13 @@ typedef struct fd_grid_desc {
 
 /* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
 typedef struct fd_shot {
-    int nsrc;                  /* >= 1 */
+    int nsrc;                  /* >= 0 for fd_forward and fd_adjoint (0: nothing injected,
+                                  an initial-value problem; src pointers may be NULL);
+                                  >= 1 for fd_gradient and fd_submit */
     const double *src_xyz;     /* host, [nsrc][ndim] */
     const float *src_wavelet;  /* device, [nt][nsrc]; row n enters u^{n+1} */
-    int nrec;                  /* >= 1 */
+    int nrec;                  /* >= 0 for fd_forward and fd_adjoint (0: no traces; rec
+                                  pointers may be NULL); >= 1 for fd_gradient and fd_submit */
     const double *rec_xyz;     /* host, [nrec][ndim] */
 } fd_shot;
 

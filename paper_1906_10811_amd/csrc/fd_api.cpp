@@ -482,12 +482,13 @@ void axis_weights(double t, int n, int r, double beta, AxisWeights &o) {
 int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s) {
     const int ndim = g->d.ndim;
     const int cap = side == 0 ? g->wp.cap_src : g->wp.cap_rec;
-    if (npts < 1) return fdi_fail(FD_ERR_ARG, "%s count must be >= 1", side ? "receiver" : "source");
+    if (npts < 0) return fdi_fail(FD_ERR_ARG, "%s count must be >= 0", side ? "receiver" : "source");
     if (npts > cap)
         return fdi_fail(FD_ERR_ARG, "%d %s exceed the grid's capacity %d", npts,
                         side ? "receivers" : "sources", cap);
-    if (!xyz) return fdi_fail(FD_ERR_ARG, "null coordinates");
-    std::vector<double> key(xyz, xyz + (size_t)npts * ndim);
+    if (npts > 0 && !xyz) return fdi_fail(FD_ERR_ARG, "null coordinates");
+    std::vector<double> key;   // (no points: empty tables, nothing injected or sampled)
+    if (npts > 0) key.assign(xyz, xyz + (size_t)npts * ndim);
     if (g->cached_n[side] == npts && g->cached_xyz[side] == key) return FD_OK;
 
     const Layout &L = g->L;
@@ -582,8 +583,10 @@ int ensure_side(fd_grid *g, int side, int npts, const double *xyz, hipStream_t s
     const size_t *off = side == 0 ? g->wp.src : g->wp.rec;
     char *st = g->stage + (side == 0 ? g->wp.stage_src : g->wp.stage_rec);
     const size_t base = off[0];
-    memcpy(st + (off[0] - base), idx.data(), sizeof(long long) * idx.size());
-    memcpy(st + (off[1] - base), w.data(), sizeof(float) * w.size());
+    if (!idx.empty()) {
+        memcpy(st + (off[0] - base), idx.data(), sizeof(long long) * idx.size());
+        memcpy(st + (off[1] - base), w.data(), sizeof(float) * w.size());
+    }
     memcpy(st + (off[2] - base), pptr.data(), sizeof(int) * pptr.size());
     if (!corners.empty()) {
         memcpy(st + (off[3] - base), corners.data(), sizeof(int4) * corners.size());
@@ -720,9 +723,12 @@ int check_dt(const fd_grid *g, double dt, int nt) {
     return FD_OK;
 }
 
-int check_shot(const fd_grid *g, const fd_shot *sh) {
+// empty_ok: a forward or adjoint run may have no sources (an initial-value
+// problem) or no receivers (only the final state wanted)
+int check_shot(const fd_grid *g, const fd_shot *sh, bool empty_ok = false) {
     if (!sh) return fdi_fail(FD_ERR_ARG, "null shot");
-    if (sh->nsrc < 1 || sh->nrec < 1) return fdi_fail(FD_ERR_ARG, "nsrc and nrec must be >= 1");
+    if (sh->nsrc < 0 || sh->nrec < 0) return fdi_fail(FD_ERR_ARG, "nsrc and nrec must be >= 0");
+    if (!empty_ok && (sh->nsrc < 1 || sh->nrec < 1)) return fdi_fail(FD_ERR_ARG, "nsrc and nrec must be >= 1");
     (void)g;
     return FD_OK;
 }
@@ -1064,9 +1070,9 @@ int fdi_forward_steps(fd_grid *g, const fd_shot *sh, int nt, int n0, int n1, flo
 int fdi_forward_prepare(fd_grid *g, const fd_shot *sh, int nt, double dt, hipStream_t s) {
     int rc;
     if (!g) return fdi_fail(FD_ERR_ARG, "null grid");
-    if ((rc = check_shot(g, sh))) return rc;
+    if ((rc = check_shot(g, sh, true))) return rc;
     if ((rc = check_dt(g, dt, nt))) return rc;
-    if (nt > 0 && !sh->src_wavelet) return fdi_fail(FD_ERR_ARG, "null wavelet");
+    if (nt > 0 && sh->nsrc > 0 && !sh->src_wavelet) return fdi_fail(FD_ERR_ARG, "null wavelet");
     if ((rc = ensure_dt(g, dt, s))) return rc;
     if ((rc = ensure_side(g, 0, sh->nsrc, sh->src_xyz, s))) return rc;
     if ((rc = ensure_side(g, 1, sh->nrec, sh->rec_xyz, s))) return rc;
@@ -1094,7 +1100,7 @@ extern "C" int fd_forward(fd_grid *g, const fd_shot *sh, int nt, double dt, floa
     hipStream_t s = (hipStream_t)stream;
     int rc;
     if ((rc = fdi_forward_prepare(g, sh, nt, dt, s))) return rc;
-    if (nt > 0 && !rec_out) return fdi_fail(FD_ERR_ARG, "null receiver output");
+    if (nt > 0 && sh->nrec > 0 && !rec_out) return fdi_fail(FD_ERR_ARG, "null receiver output");
     const Layout &L = g->L;
     if (opts && opts->u0) HIPCHK(launch_dense_to_field(L, opts->u0, g->uA, g->st, g->amp, s));
     else HIPCHK(launch_zero_field(L, g->uA, g->st, s));
@@ -1126,9 +1132,10 @@ extern "C" int fd_adjoint(fd_grid *g, const fd_shot *sh, int nt, double dt,
     API_GUARD_BEGIN
     if (!g) return fdi_fail(FD_ERR_ARG, "null grid");
     int rc;
-    if ((rc = check_shot(g, sh))) return rc;
+    if ((rc = check_shot(g, sh, true))) return rc;
     if ((rc = check_dt(g, dt, nt))) return rc;
-    if (nt > 0 && (!residual || !src_adj)) return fdi_fail(FD_ERR_ARG, "null residual or output");
+    if (nt > 0 && ((sh->nrec > 0 && !residual) || (sh->nsrc > 0 && !src_adj)))
+        return fdi_fail(FD_ERR_ARG, "null residual or output");
     DeviceGuard dg(g->device);
     hipStream_t s = (hipStream_t)stream;
     if ((rc = ensure_dt(g, dt, s))) return rc;

@@ -115,3 +115,38 @@ def test_extreme_z_chunks(shape, zchunk):
     e_u = rel_l2(state[0].cpu().numpy(), u_nt)
     print("zchunk %d on %s: traces %.3e field %.3e" % (zchunk, shape, e_rec, e_u), flush=True)
     assert e_rec <= TOL and e_u <= TOL
+
+
+def test_shots_without_sources_or_receivers():
+    """No sources (an initial-value problem from a caller's u^0 = u^{-1}) and
+    no receivers (only the final state) against the oracle; the adjoint of
+    an empty receiver set is zero and of an empty source set is empty."""
+    need_gpu()
+    c = case((44, 36, 30), 8, 5, 50, seed=31, nsrc=1, nrec=7)
+    dev = torch.device("cuda:0")
+    x = np.linspace(-1.0, 1.0, c["og"].array_shape[2])
+    bump = np.exp(-((x[None, None, :] ** 2 + np.linspace(-1, 1, c["og"].array_shape[1])[None, :, None] ** 2
+                     + np.linspace(-1, 1, c["og"].array_shape[0])[:, None, None] ** 2) / 0.05))
+    no_src = dict(c, src=np.zeros((0, 3)), wav=np.zeros((c["nt"], 0), dtype=np.float32))
+    want, u_nt, _, _ = oracle_forward(no_src, u0=bump, u_prev=bump)
+    g = gpu_grid(c)
+    u0 = torch.from_numpy(bump.astype(np.float32)).to(dev)
+    rec, (u, _) = g.forward(no_src["src"], torch.zeros((c["nt"], 0), device=dev), c["rec"], c["dt"],
+                            u0=u0, u_prev=u0, save_state=True)
+    torch.cuda.synchronize()
+    assert rec.shape == (c["nt"], len(c["rec"]))
+    assert rel_l2(rec.cpu().numpy(), want) <= TOL
+    assert rel_l2(u.cpu().numpy(), u_nt) <= TOL
+    want2, u2, _, _ = oracle_forward(c)
+    rec0, (v, _) = g.forward(c["src"], torch.from_numpy(c["wav"]).to(dev), np.zeros((0, 3)), c["dt"],
+                             save_state=True)
+    torch.cuda.synchronize()
+    assert rec0.shape == (c["nt"], 0)
+    assert rel_l2(v.cpu().numpy(), u2) <= TOL
+    res = torch.zeros((c["nt"], 0), device=dev)
+    fa = g.adjoint(c["src"], np.zeros((0, 3)), res, c["dt"])
+    fb = g.adjoint(np.zeros((0, 3)), c["rec"], torch.ones((c["nt"], len(c["rec"])), device=dev), c["dt"])
+    torch.cuda.synchronize()
+    assert fa.shape == (c["nt"], 1) and not bool(fa.any())
+    assert fb.shape == (c["nt"], 0)
+    g.close()
