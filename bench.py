@@ -415,6 +415,8 @@ def bench_serving(torch, n=64, slots=6, budget_gib=2.0, roomy_gib=32.0):
       *_shortest_first    the same two with the shortest-remaining-work
                           policy (at most two chunks on the device, for the
                           requests with the least remaining point-steps);
+      *_response_ratio    the same two ordered by the response ratio
+                          (age + remaining time) / remaining time;
       saturated_*         all requests at t = 0, one slot and `slots` slots
                           (throughput without arrival gaps)."""
     from paper_1906_10811_amd import Server
@@ -461,6 +463,8 @@ def bench_serving(torch, n=64, slots=6, budget_gib=2.0, roomy_gib=32.0):
     out["batched_budget"] = run(budget_gib, slots, arrivals)
     out["batched_shortest_first"] = run(roomy_gib, slots, arrivals, policy="shortest")
     out["batched_budget_shortest_first"] = run(budget_gib, slots, arrivals, policy="shortest")
+    out["batched_response_ratio"] = run(roomy_gib, slots, arrivals, policy="ratio")
+    out["batched_budget_response_ratio"] = run(budget_gib, slots, arrivals, policy="ratio")
     out["saturated_one_slot"] = sat1
     out["saturated_batched"] = run(roomy_gib, slots, zeros)
     return out

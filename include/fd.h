@@ -319,11 +319,17 @@ typedef struct fd_server_desc {
                                   chunks, both for the resident request with the fewest
                                   remaining point-steps while it has steps left (a short shot
                                   arriving behind a long one overtakes it at the next chunk
-                                  boundary) */
+                                  boundary);
+                                  FD_SERVE_RATIO (2): as FD_SERVE_SHORTEST, ordered by the
+                                  response ratio (age since submission + remaining time) /
+                                  remaining time, the remaining time from the device's
+                                  measured point-step rate: short shots still go first, and a
+                                  long one that has waited is no longer passed */
 } fd_server_desc;
 
 #define FD_SERVE_SHARE 0
 #define FD_SERVE_SHORTEST 1
+#define FD_SERVE_RATIO 2
 
 typedef struct fd_request {
     fd_grid_desc grid;         /* grid of this shot */

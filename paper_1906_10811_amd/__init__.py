@@ -296,16 +296,19 @@ class Server:
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, steps_per_round: int = 0, device: int = 0,
                  policy: str = "share"):
         """policy: "share" (every resident request advances as its previous
-        chunk completes) or "shortest" (preemptive shortest remaining work
+        chunk completes), "shortest" (preemptive shortest remaining work
         first: the device holds at most two chunks, both for the request with
-        the least remaining work)."""
+        the least remaining work) or "ratio" (the same, ordered by the
+        response ratio (age + remaining time) / remaining time, so that a long
+        request that has waited is no longer passed)."""
         lib = _lib.load()
         d = _lib.ServerDesc()
         d.device = int(device)
         d.hbm_budget_bytes = int(hbm_budget_bytes)
         d.max_slots = int(max_slots)
         d.steps_per_round = int(steps_per_round)
-        d.policy = {"share": _lib.FD_SERVE_SHARE, "shortest": _lib.FD_SERVE_SHORTEST}[policy]
+        d.policy = {"share": _lib.FD_SERVE_SHARE, "shortest": _lib.FD_SERVE_SHORTEST,
+                    "ratio": _lib.FD_SERVE_RATIO}[policy]
         h = ctypes.c_void_p()
         _lib.check(lib.fd_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

@@ -32,6 +32,7 @@ FD_ACT_ADVANCE, FD_ACT_STORE, FD_ACT_RESTORE, FD_ACT_YOUTURN = 1, 2, 3, 4
 
 FD_SERVE_SHARE = 0
 FD_SERVE_SHORTEST = 1
+FD_SERVE_RATIO = 2
 
 # every symbol include/fd.h declares
 EXPORTS = (

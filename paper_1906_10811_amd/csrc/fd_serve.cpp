@@ -18,7 +18,12 @@
 // point-steps (preemptive shortest remaining work first, at chunk
 // granularity): a shot large enough to fill the GPU gains nothing from
 // sharing it, equal shares delay every shot, and this order lets short
-// shots pass long ones.  Each request runs the same kernels with the same
+// shots pass long ones.  The response-ratio policy orders the same way by
+// (age + remaining time) / remaining time instead (highest response ratio
+// next, preemptive at chunk granularity; the remaining time is the remaining
+// point-steps over the device's measured rate): a short request still goes
+// first, but a long one that has waited long enough is no longer passed, so
+// the tail does not grow.  Each request runs the same kernels with the same
 // launch geometry as a lone fd_forward, so its result does not depend on the
 // mix it ran in or the policy.
 #include <hip/hip_runtime.h>
@@ -121,6 +126,7 @@ struct Req {
     double pts = 0;      // padded points of the grid (remaining work = pts * (nt - next_step))
     int next_step = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the chunks in flight, oldest at ev_head
+    int ev_steps[2] = {0, 0};                // steps of those chunks
     int ev_head = 0, ev_count = 0;
     fd_result res{};
     std::string msg;   // error message of a failed request
@@ -300,6 +306,10 @@ void fd_server::run_scheduler() {
     (void)hipSetDevice(d.device);
     const int chunk = d.steps_per_round > 0 ? d.steps_per_round : 50;
     std::vector<Req *> active;
+    // device rate in point-steps per second, from the completion times of
+    // chunks while the device is busy (the first chunk after an idle period
+    // is timed from its enqueue)
+    double rate = 0.0, t_prev = -1.0;
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -324,6 +334,12 @@ void fd_server::run_scheduler() {
             while (r->ev_count > 0) {
                 const hipError_t q = hipEventQuery(r->ev[r->ev_head]);
                 if (q == hipErrorNotReady) break;
+                const double t = now();
+                if (q == hipSuccess && t_prev >= 0.0 && t > t_prev) {
+                    const double sample = r->pts * r->ev_steps[r->ev_head] / (t - t_prev);
+                    rate = rate > 0.0 ? 0.8 * rate + 0.2 * sample : sample;
+                }
+                t_prev = t;
                 r->ev_head ^= 1;
                 --r->ev_count;
                 progressed = true;
@@ -341,7 +357,11 @@ void fd_server::run_scheduler() {
                 ++i;
             }
         }
+        int on_device = 0;
+        for (const Req *r : active) on_device += r->ev_count;
+        if (on_device == 0) t_prev = -1.0;   // idle: the next completion is timed from its enqueue
         auto enqueue = [&](Req *r) -> bool {
+            if (t_prev < 0.0) t_prev = now();
             hipStream_t s = streams[r->slot];
             fd_shot sh{r->nsrc, r->src.data(), r->d_wav, r->nrec, r->rec.data()};
             const int n1 = std::min(r->nt, r->next_step + chunk);
@@ -355,14 +375,25 @@ void fd_server::run_scheduler() {
                 to_finishing(r, status);
                 return false;
             }
+            r->ev_steps[(r->ev_head + r->ev_count) & 1] = n1 - r->next_step;
             r->next_step = n1;
             ++r->ev_count;
             return true;
         };
-        if (d.policy == FD_SERVE_SHORTEST) {
-            std::stable_sort(active.begin(), active.end(), [](const Req *x, const Req *y) {
-                return x->pts * (x->nt - x->next_step) < y->pts * (y->nt - y->next_step);
-            });
+        if (d.policy == FD_SERVE_SHORTEST || d.policy == FD_SERVE_RATIO) {
+            if (d.policy == FD_SERVE_SHORTEST || rate <= 0.0) {
+                std::stable_sort(active.begin(), active.end(), [](const Req *x, const Req *y) {
+                    return x->pts * (x->nt - x->next_step) < y->pts * (y->nt - y->next_step);
+                });
+            } else {
+                const double t = now();
+                auto ratio = [&](const Req *x) {
+                    const double rem = x->pts * (x->nt - x->next_step) / rate;   // seconds
+                    return rem > 0.0 ? (t - x->res.t_submit + rem) / rem : 1e300;
+                };
+                std::stable_sort(active.begin(), active.end(),
+                                 [&](const Req *x, const Req *y) { return ratio(x) > ratio(y); });
+            }
             int budget = 2;
             for (const Req *r : active) budget -= r->ev_count;
             std::vector<Req *> order = active;
@@ -395,8 +426,8 @@ extern "C" int fd_server_create(const fd_server_desc *desc, fd_server **out) {
         *out = nullptr;
         if (desc->max_slots < 1 || desc->hbm_budget_bytes < 4096 || desc->steps_per_round < 0)
             return fdi_fail(FD_ERR_ARG, "max_slots >= 1, budget >= 4 KiB, steps_per_round >= 0");
-        if (desc->policy != FD_SERVE_SHARE && desc->policy != FD_SERVE_SHORTEST)
-            return fdi_fail(FD_ERR_ARG, "policy must be FD_SERVE_SHARE or FD_SERVE_SHORTEST");
+        if (desc->policy != FD_SERVE_SHARE && desc->policy != FD_SERVE_SHORTEST && desc->policy != FD_SERVE_RATIO)
+            return fdi_fail(FD_ERR_ARG, "policy must be FD_SERVE_SHARE, FD_SERVE_SHORTEST or FD_SERVE_RATIO");
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev)
             return fdi_fail(FD_ERR_ARG, "no such device %d", desc->device);

@@ -43,7 +43,7 @@ def _alone(r):
     return out
 
 
-@pytest.mark.parametrize("policy", ["share", "shortest"])
+@pytest.mark.parametrize("policy", ["share", "shortest", "ratio"])
 def test_mix_equals_alone_and_budget_holds(policy):
     need_gpu()
     from paper_1906_10811_amd import Server
