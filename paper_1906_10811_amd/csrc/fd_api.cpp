@@ -212,13 +212,16 @@ constexpr double kTileNarrowGain = 0.06;   // lane-use margin that selects 32 x 
 
 bool mixed_fits(const Layout &L) { return L.nx > 64 && L.nx % 64 != 0 && L.nx % 64 <= 32; }
 
-// Whether fd_forward runs two leapfrog levels per launch (k_step3d_t2):
-// only on request.  Measured on layered3d_256 (336^3, so 8): 312 Gpts/s
-// against 370 for one step per launch (it reads 1.41x its algorithmic
-// bytes, and with 256 registers per lane it keeps only one plane of loads
-// in flight), so the automatic choice is one step per launch.
+// Whether fd_forward runs two leapfrog levels per launch (k_step3d_t2).
+// Its recomputed ring grows with the radius: 16 % of a 64 x 16 tile at
+// radius 1, 69 % at radius 4.  Measured (float32, 400 steps), two levels
+// against one step per launch: so 2 on 336^3 427 vs 386 Gpts/s and on 280^3
+// 408 vs 365; so 4 401 vs 383 and 340 vs 360; so 6 349 vs 378 and 295 vs
+// 354; so 8 313 vs 372 and 267 vs 347.  So the automatic choice takes two
+// levels at space order 2 and one step elsewhere.
 bool t2_enabled(const fd_grid_desc *d) {
-    return d->time_block == 2 && d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR;
+    const bool avail = d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR;
+    return avail && (d->time_block == 2 || (d->time_block == 0 && d->space_order == 2));
 }
 
 // 16-bit value-and-difference storage, and the element type of a storage.

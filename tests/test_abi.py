@@ -74,6 +74,11 @@ def test_workspace_bytes_grow_with_grid(lib):
     # value-and-difference storage keeps a third 16-bit field
     rc9, b9 = _bytes(lib, _desc(shape=(64, 48, 32), storage=_lib.FD_STORE_BF16_DIFF))
     assert rc9 == 0 and b9 - b3 >= 2 * (84 * 68 * 52) and b9 < b1
+    # space order 2 in 3D float32 takes two levels per launch by default
+    rc10, b10 = _bytes(lib, _desc(shape=(64, 48, 32), so=2))
+    rc11, b11 = _bytes(lib, _desc(shape=(64, 48, 32), so=2, time_block=2))
+    rc12, b12 = _bytes(lib, _desc(shape=(64, 48, 32), so=2, time_block=1))
+    assert rc10 == rc11 == rc12 == 0 and b10 == b11 and b10 - b12 >= 2 * 4 * (84 * 68 * 52)
     rc7, b7 = _bytes(lib, _desc(shape=(64, 48, 32), so=10))
     rc8, b8 = _bytes(lib, _desc(shape=(64, 48, 32), so=10, time_block=1))
     assert rc7 == 0 and b7 == b8

@@ -139,3 +139,19 @@ def test_two_levels_through_the_server():
     srv.close()
     assert info["status"] == 0
     assert np.array_equal(out, alone.cpu().numpy())
+
+
+def test_automatic_choice_by_space_order():
+    """time_block 0 runs two levels per launch at space order 2 (3D float32)
+    and one step elsewhere; either way the results are the oracle's."""
+    need_gpu()
+    for so, want in ((2, 2), (4, 1), (8, 1)):
+        c = case((66, 40, 30), so, 4, 31, seed=90 + so, nsrc=2, nrec=7)
+        g = gpu_grid(c)
+        assert g.time_block == want, (so, g.time_block)
+        _, rec = gpu_forward(c, grid=g)
+        g.close()
+        ref, _, _, _ = oracle_forward(c)
+        assert_traces(rec.cpu().numpy(), ref, TOL, "so %d, automatic time_block %d" % (so, want))
+    c = case((66, 40, 30), 2, 4, 20, seed=3)
+    assert gpu_grid(c, storage="bf16").time_block == 1
