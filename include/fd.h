@@ -84,6 +84,26 @@ typedef enum fd_storage {
     FD_STORE_BF16_DIFF = 4
 } fd_storage;
 
+/* Storage of the parameter p = dt^2 v^2 that multiplies the Laplacian in the
+   update above.  It is read once per point-step: 4 of the 16 bytes of a
+   float32 step.  A storage form of this library, not of the thesis. */
+typedef enum fd_param_storage {
+    FD_PARAM_F32 = 0,      /* float32 p, rounded once from dt^2 v^2 */
+    /* 16-bit code of p on a uniform scale between its extremes: p0 =
+       dt^2 v_min^2 and dp = dt^2 (v_max^2 - v_min^2) / 65535, both rounded to
+       float32; code = the nearest integer in [0, 65535] to (p - p0) / dp,
+       evaluated in float64 from p = dt^2 v^2; the step uses
+       fma(code, dp, p0) in float32.  Any velocity range fits, and a point's
+       p moves by at most dp / 2 plus one float32 rounding (relative: 2^-17
+       (v_max^2 - v_min^2) / v_min^2, 6e-5 for 1.5-4.5 km/s): a fixed
+       perturbation of the medium, not an error that grows with the steps.
+       The step then moves 14 B per point-step with float32 wavefields, 8 B
+       with two 16-bit levels and 10 B with the 16-bit value and difference.
+       3D fd_forward, fd_adjoint and the server; fd_gradient refuses it, and
+       two levels per launch are not available with it. */
+    FD_PARAM_Q16 = 1
+} fd_param_storage;
+
 /* Grid description (Devito Grid + TimeFunction, Section 2.1.1). */
 typedef struct fd_grid_desc {
     int ndim;              /* 2 or 3 */
@@ -122,6 +142,7 @@ typedef struct fd_grid_desc {
                               step elsewhere, where the recomputed ring of the two-level
                               kernel costs more than the traffic it saves); anything
                               else, or 2 where it is not available, is FD_ERR_ARG */
+    int param_storage;     /* fd_param_storage; FD_PARAM_Q16 in 3D only */
 } fd_grid_desc;
 
 /* Sources and receivers of one shot (Devito SparseTimeFunction, Section 2.1.1). */
@@ -159,6 +180,9 @@ typedef struct fd_grid_info {
                               beside 64 x 16 ones, else 0 */
     int zchunk;            /* 3D: z planes per workgroup of a plain step; 2D: 64 */
     int time_block;        /* steps per launch of fd_forward (1 or 2) */
+    int param_storage;     /* fd_param_storage in use */
+    double param_base;     /* FD_PARAM_Q16: p0 and dp of the latest dt (float32 values), */
+    double param_step;     /* 0 before the first call that steps or with FD_PARAM_F32 */
 } fd_grid_info;
 
 typedef struct fd_grid fd_grid;

@@ -24,6 +24,7 @@ __all__ = ["Grid", "Server", "FDError", "modeling", "diffusion", "diffusion_dt_l
 
 _STORAGE = {"f32": _lib.FD_STORE_F32, "f16": _lib.FD_STORE_F16, "bf16": _lib.FD_STORE_BF16,
             "f16_diff": _lib.FD_STORE_F16_DIFF, "bf16_diff": _lib.FD_STORE_BF16_DIFF}
+_PARAM = {"f32": _lib.FD_PARAM_F32, "q16": _lib.FD_PARAM_Q16}
 
 
 def build() -> str:
@@ -55,13 +56,17 @@ class Grid:
 
     storage: "f32", "f16", "bf16" (two 16-bit time levels), or, in 3D,
     "f16_diff" / "bf16_diff" (the level and its difference from the
-    previous one, both 16-bit)."""
+    previous one, both 16-bit).
+
+    param: "f32" (p = dt^2 v^2 in float32) or, in 3D, "q16" (16-bit codes
+    on a uniform scale from dt^2 v_min^2 to dt^2 v_max^2; forward and
+    adjoint only)."""
 
     def __init__(self, shape, spacing, vp: torch.Tensor, space_order: int = 8, nbl: int = 0,
                  origin=None, damp_max: float = 0.0, storage: str = "f32", amp_scale: float = 0.0,
                  vp_padded: bool = False, max_src: int = 0, max_rec: int = 0, zchunk: int = 0,
                  sinc_radius: int = 0, sinc_beta: float = 0.0, tile_x: int = 0, time_block: int = 0,
-                 stream=None):
+                 param: str = "f32", stream=None):
         lib = _lib.load()
         ndim = len(shape)
         self.ndim = ndim
@@ -84,6 +89,7 @@ class Grid:
         d.sinc_beta = float(sinc_beta)
         d.tile_x = int(tile_x)
         d.time_block = int(time_block)
+        d.param_storage = _PARAM[param]
         self.desc = d
         nbytes = ctypes.c_size_t()
         _lib.check(lib.fd_grid_workspace_bytes(ctypes.byref(d), ctypes.byref(nbytes)))
@@ -110,6 +116,13 @@ class Grid:
         self.tile_strip = int(info.tile_strip)
         self.zchunk = int(info.zchunk)
         self.time_block = int(info.time_block)
+
+    def param_scale(self):
+        """(p0, dp) of the 16-bit p codes for the latest dt, (0, 0) before
+        the first step or with float32 p."""
+        info = _lib.GridInfo()
+        _lib.check(_lib.load().fd_grid_get_info(self._h, ctypes.byref(info)))
+        return info.param_base, info.param_step
 
     @property
     def array_shape(self):
@@ -316,7 +329,7 @@ class Server:
 
     @staticmethod
     def _request(shape, spacing, space_order, nbl, vp, src_xyz, wavelet, rec_xyz, dt, storage="f32",
-                 origin=None, amp_scale=0.0, sinc_radius=0, sinc_beta=0.0, time_block=0):
+                 origin=None, amp_scale=0.0, sinc_radius=0, sinc_beta=0.0, time_block=0, param="f32"):
         ndim = len(shape)
         r = _lib.Request()
         g = r.grid
@@ -332,6 +345,7 @@ class Server:
         g.sinc_radius = int(sinc_radius)
         g.sinc_beta = float(sinc_beta)
         g.time_block = int(time_block)
+        g.param_storage = _PARAM[param]
         vp = np.ascontiguousarray(vp, dtype=np.float32)
         src = _coords(src_xyz, ndim)
         rec = _coords(rec_xyz, ndim)

@@ -24,6 +24,9 @@ FD_STORE_BF16 = 2
 FD_STORE_F16_DIFF = 3
 FD_STORE_BF16_DIFF = 4
 
+FD_PARAM_F32 = 0
+FD_PARAM_Q16 = 1
+
 FD_GRAD_RESIDUAL_GIVEN = 1
 FD_GRAD_BINOMIAL = 2
 FD_GRAD_VELOCITY = 4
@@ -63,6 +66,7 @@ class GridDesc(ctypes.Structure):
         ("sinc_beta", ctypes.c_double),
         ("tile_x", ctypes.c_int),
         ("time_block", ctypes.c_int),
+        ("param_storage", ctypes.c_int),
     ]
 
 
@@ -98,6 +102,9 @@ class GridInfo(ctypes.Structure):
         ("tile_strip", ctypes.c_int),
         ("zchunk", ctypes.c_int),
         ("time_block", ctypes.c_int),
+        ("param_storage", ctypes.c_int),
+        ("param_base", ctypes.c_double),
+        ("param_step", ctypes.c_double),
     ]
 
 

@@ -117,8 +117,14 @@ bool fdi_check_desc(const fd_grid_desc *d) {
         return fdi_fail(FD_ERR_ARG, "sinc_radius must be 0..%d", kMaxSincR), false;
     if (!std::isfinite(d->sinc_beta)) return fdi_fail(FD_ERR_ARG, "sinc_beta"), false;
     if (d->time_block < 0 || d->time_block > 2) return fdi_fail(FD_ERR_ARG, "time_block must be 0, 1 or 2"), false;
-    if (d->time_block == 2 && !(d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR))
-        return fdi_fail(FD_ERR_ARG, "time_block 2 needs a 3D float32 grid of space order <= %d", 2 * kT2MaxR),
+    if (d->param_storage != FD_PARAM_F32 && d->param_storage != FD_PARAM_Q16)
+        return fdi_fail(FD_ERR_ARG, "param_storage must be FD_PARAM_F32 or FD_PARAM_Q16"), false;
+    if (d->param_storage == FD_PARAM_Q16 && d->ndim != 3)
+        return fdi_fail(FD_ERR_ARG, "the 16-bit p code is 3D only"), false;
+    if (d->time_block == 2 && !(d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR &&
+                                d->param_storage == FD_PARAM_F32))
+        return fdi_fail(FD_ERR_ARG, "time_block 2 needs a 3D float32 grid of space order <= %d with float32 p",
+                        2 * kT2MaxR),
                false;
     long long pts = 1;
     for (int a = 0; a < d->ndim; ++a) pts *= (long long)d->shape[a] + 2LL * d->nbl;
@@ -220,7 +226,8 @@ bool mixed_fits(const Layout &L) { return L.nx > 64 && L.nx % 64 != 0 && L.nx % 
 // 354; so 8 313 vs 372 and 267 vs 347.  So the automatic choice takes two
 // levels at space order 2 and one step elsewhere.
 bool t2_enabled(const fd_grid_desc *d) {
-    const bool avail = d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR;
+    const bool avail = d->ndim == 3 && d->storage == FD_STORE_F32 && d->space_order <= 2 * kT2MaxR &&
+                       d->param_storage == FD_PARAM_F32;
     return avail && (d->time_block == 2 || (d->time_block == 0 && d->space_order == 2));
 }
 
@@ -287,7 +294,7 @@ WsPlan plan(const fd_grid_desc *d, const Layout &L) {
     const size_t f32 = align_up((size_t)L.elems * 4, 256);
     size_t o = 0;
     w.vel = o; o += f32;
-    w.p = o; o += f32;
+    w.p = o; o += d->param_storage == FD_PARAM_Q16 ? align_up((size_t)L.elems * 2, 256) : f32;
     w.uA = o; o += w.field_bytes;
     w.uB = o; o += w.field_bytes;
     const bool t2 = t2_enabled(d);
@@ -334,14 +341,16 @@ struct fd_grid {
     size_t ws_bytes;
     WsPlan wp;
     float *vel, *p, *damp;
+    uint16_t *pq;          // FD_PARAM_Q16: the codes of p (p is then null)
+    float pq_base, pq_step;
     void *uA, *uB;
     double *partials;
-    unsigned *vmax_bits;
+    unsigned *vmax_bits;   // [0] max, [1] min of v (bits)
     SparseDev sd[2];       // 0 = sources, 1 = receivers
     std::vector<double> cached_xyz[2];
     int cached_n[2];
     int ncorner[2];        // injection corners in the current tables
-    double vmax, dt_crit, sigma_max;
+    double vmax, vmin, dt_crit, sigma_max;
     double dt_cached;
     char *stage;
     hipEvent_t stage_ev;
@@ -422,7 +431,17 @@ int ensure_dt(fd_grid *g, double dt, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(g->damp, tab, sizeof(float) * o, hipMemcpyHostToDevice, s));
     rc = stage_release(g, s);
     if (rc) return rc;
-    HIPCHK(launch_make_p(L, g->vel, dt, g->p, s));
+    if (g->pq) {
+        // p0 = dt^2 v_min^2 and dp = (dt^2 v_max^2 - p0) / 65535 as the
+        // float32 values the step decodes with
+        const double dt2 = dt * dt;
+        const double pmin = dt2 * g->vmin * g->vmin, pmax = dt2 * g->vmax * g->vmax;
+        g->pq_base = (float)pmin;
+        g->pq_step = (float)((pmax - pmin) / 65535.0);
+        HIPCHK(launch_make_pq(L, g->vel, dt, g->pq_base, g->pq_step, g->pq, s));
+    } else {
+        HIPCHK(launch_make_p(L, g->vel, dt, g->p, s));
+    }
     g->dt_cached = dt;
     return FD_OK;
 }
@@ -653,6 +672,9 @@ StepArgs base_args(const fd_grid *g) {
     StepArgs a{};
     a.L = g->L;
     a.p = g->p;
+    a.pq = g->pq;
+    a.pq_base = g->pq_base;
+    a.pq_step = g->pq_step;
     a.damp = g->damp;
     const double *h = g->d.spacing;
     const double hx2 = h[0] * h[0];
@@ -779,7 +801,9 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
     g->ws_bytes = ws_bytes;
     g->wp = wp;
     g->vel = (float *)(g->ws + wp.vel);
-    g->p = (float *)(g->ws + wp.p);
+    const bool q16 = desc->param_storage == FD_PARAM_Q16;
+    g->p = q16 ? nullptr : (float *)(g->ws + wp.p);
+    g->pq = q16 ? (uint16_t *)(g->ws + wp.p) : nullptr;
     g->uA = g->ws + wp.uA;
     g->uB = g->ws + wp.uB;
     g->t2 = t2_enabled(desc);
@@ -857,7 +881,7 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
                 cus = 256;
             // (the forward slot runs the difference step under the difference storages)
             const int mk = (m == kPlain && g->diff) ? (int)kDiff : m;
-            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, mk, g->shape3));
+            const int occ = std::max(1, step_blocks_per_cu(3, L.r, g->st, mk, g->shape3, g->pq != nullptr));
             const int tiles = std::max(1, g->ntx * g->nty + g->nstrip);
             const int kmax = std::min(occ, 3), prefer = g->st == Store::F32 ? 2 : 3;
             int nzc = 1;
@@ -907,23 +931,27 @@ extern "C" int fd_grid_create(const fd_grid_desc *desc, void *workspace, size_t 
         ((g->t2 || g->diff) && (e = launch_zero_field(L, g->uC, g->st, s)) != hipSuccess) ||
         (g->t2 && (e = launch_zero_field(L, g->uD, g->st, s)) != hipSuccess) ||
         (e = launch_zero_field(L, g->vel, Store::F32, s)) != hipSuccess ||
-        (e = launch_zero_field(L, g->p, Store::F32, s)) != hipSuccess)
+        (e = (g->pq ? launch_zero_field(L, g->pq, Store::F16, s) : launch_zero_field(L, g->p, Store::F32, s))) !=
+            hipSuccess)
         return cleanup(fdi_fail(FD_ERR_DEVICE, "zero fill: %s", hipGetErrorString(e)));
     const int phys[3] = {desc->shape[0], desc->ndim == 3 ? desc->shape[1] : 1,
                          desc->ndim == 3 ? desc->shape[2] : desc->shape[1]};
     if ((e = launch_fill_velocity(L, vp_dev, desc->vp_padded, desc->nbl, phys, g->vel, s)) != hipSuccess ||
         (e = hipMemsetAsync(g->vmax_bits, 0, sizeof(unsigned), s)) != hipSuccess ||
-        (e = launch_vmax(L, g->vel, g->vmax_bits, s)) != hipSuccess)
+        (e = hipMemsetD32Async((hipDeviceptr_t)(g->vmax_bits + 1), 0x7F800000u, 1, s)) != hipSuccess ||
+        (e = launch_vrange(L, g->vel, g->vmax_bits, s)) != hipSuccess)
         return cleanup(fdi_fail(FD_ERR_DEVICE, "velocity setup: %s", hipGetErrorString(e)));
-    unsigned bits = 0;
-    if ((e = hipMemcpyAsync(&bits, g->vmax_bits, sizeof bits, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+    unsigned bits[2] = {0, 0};
+    if ((e = hipMemcpyAsync(bits, g->vmax_bits, sizeof bits, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return cleanup(fdi_fail(FD_ERR_DEVICE, "velocity readback: %s", hipGetErrorString(e)));
-    float vmax;
-    memcpy(&vmax, &bits, sizeof vmax);
+    float vmax, vmin;
+    memcpy(&vmax, &bits[0], sizeof vmax);
+    memcpy(&vmin, &bits[1], sizeof vmin);
     if (!(vmax > 0.f) || !std::isfinite(vmax))
         return cleanup(fdi_fail(FD_ERR_ARG, "velocity must be finite and > 0 everywhere"));
     g->vmax = vmax;
+    g->vmin = vmin;
     // von Neumann limit: dt_crit = 1 / (v_max sqrt(sum_{j odd} c_j * sum_a h_a^-2))
     double s_odd = 0.0;
     for (int j = 1; j <= L.r; j += 2) s_odd += g->c[j];
@@ -978,6 +1006,9 @@ extern "C" int fd_grid_get_info(const fd_grid *g, fd_grid_info *info) {
     info->tile_strip = g->nstrip > 0 ? g->L.nx - 64 * g->ntx : 0;
     info->zchunk = g->zchunk[kPlain];
     info->time_block = g->t2 ? 2 : 1;
+    info->param_storage = g->d.param_storage;
+    info->param_base = g->pq && g->dt_cached > 0.0 ? g->pq_base : 0.0;
+    info->param_step = g->pq && g->dt_cached > 0.0 ? g->pq_step : 0.0;
     return FD_OK;
 }
 
@@ -1237,6 +1268,7 @@ extern "C" int fd_gradient(fd_grid *g, const fd_shot *sh, int nt, double dt, con
     if (flags & ~(FD_GRAD_RESIDUAL_GIVEN | FD_GRAD_BINOMIAL | FD_GRAD_VELOCITY))
         return fdi_fail(FD_ERR_ARG, "unknown fd_gradient flag");
     if (g->st != Store::F32) return fdi_fail(FD_ERR_ARG, "fd_gradient needs float32 storage");
+    if (g->pq) return fdi_fail(FD_ERR_ARG, "fd_gradient needs float32 p (FD_PARAM_F32)");
     if (!d_obs || !misfit || !grad_m || !workspace || !sh->src_wavelet)
         return fdi_fail(FD_ERR_ARG, "null pointer argument");
     if ((uintptr_t)workspace % 256) return fdi_fail(FD_ERR_ARG, "workspace must be 256-byte aligned");

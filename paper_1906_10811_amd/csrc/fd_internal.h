@@ -113,7 +113,9 @@ struct StepArgs {
     const void *u;          // centre field (read, with halo)
     const void *prev;       // previous field (read)
     void *out;              // new field (may alias prev: in-place update)
-    const float *p;         // dt^2 v^2, pitched FP32
+    const float *p;         // dt^2 v^2, pitched FP32 (null when pq is set)
+    const uint16_t *pq;     // 16-bit code of p, pitched: p = fma(code, pq_step, pq_base)
+    float pq_base, pq_step;
     const float *damp;      // sigma dt/2 per index: [nx] x, then [ny] y, then [nz] z
     float w0;               // centre weight sum_a c_0 / h_a^2
     float wx[kMaxR + 1];    // c_j / h_x^2
@@ -141,9 +143,10 @@ struct StepArgs {
 enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
 
 // Resident workgroups per CU of a step kernel (0 if unknown).
-int step_blocks_per_cu(int ndim, int r, Store st, int mode, int shape3);
+int step_blocks_per_cu(int ndim, int r, Store st, int mode, int shape3, bool pq);
 
 // Launchers (fd_kernels.hip).  Each returns the hipError_t of the launch.
+// launch_step reads p from a.pq when that is set (3D, kPlain and kDiff).
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s);
 // Two leapfrog levels in one launch (3D, float32, radius <= kT2MaxR): 64 x
 // 16 tiles (a.ntx, a.nty), a.ntz z chunks of a.zchunk planes; a.inj points
@@ -155,8 +158,14 @@ int step_t2_blocks_per_cu(int r);
 hipError_t launch_sample(const Sample &smp, const void *field, Store st, hipStream_t s);
 hipError_t launch_fill_velocity(const Layout &L, const float *vp, int vp_padded, int nbl,
                                 const int *phys, float *vel, hipStream_t s);
-hipError_t launch_vmax(const Layout &L, const float *vel, unsigned *out_bits, hipStream_t s);
+// out_bits[0] = bits of max v, out_bits[1] = bits of min v over the grid
+// points (positive floats order as their bits); the caller sets them to 0
+// and to the bits of +inf first.
+hipError_t launch_vrange(const Layout &L, const float *vel, unsigned *out_bits, hipStream_t s);
 hipError_t launch_make_p(const Layout &L, const float *vel, double dt, float *p, hipStream_t s);
+// code = nearest integer in [0, 65535] to (dt^2 v^2 - base) / step, float64
+hipError_t launch_make_pq(const Layout &L, const float *vel, double dt, double base, double step,
+                          uint16_t *pq, hipStream_t s);
 hipError_t launch_zero_field(const Layout &L, void *f, Store st, hipStream_t s);
 hipError_t launch_dense_to_field(const Layout &L, const float *dense, void *f, Store st,
                                  float scale, hipStream_t s);

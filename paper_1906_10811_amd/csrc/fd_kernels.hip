@@ -129,6 +129,16 @@ __device__ inline float comp(const float4 &v, int i) {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
 
+// p = dt^2 v^2 of 4 points: float32 as stored, or the 16-bit codes c of
+// the quantised form, p = fma(c, step, base) in float32.
+__device__ inline float4 param4(const float4 &v, float, float) { return v; }
+__device__ inline float4 param4(const uint2 &c, float base, float step) {
+    return make_float4(__builtin_fmaf((float)(c.x & 0xFFFFu), step, base),
+                       __builtin_fmaf((float)(c.x >> 16), step, base),
+                       __builtin_fmaf((float)(c.y & 0xFFFFu), step, base),
+                       __builtin_fmaf((float)(c.y >> 16), step, base));
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin by hardware id.  Renumber
 // so that each XCD runs one contiguous range of logical tiles: x-neighbour
 // and y-neighbour tiles then share an L2, which serves their halo reads.
@@ -292,8 +302,9 @@ struct Smem3 {
 // One workgroup's step: the xy tile at (x0, y0) of TW float4 columns per
 // row (16: 64 x 16 points, 8: 32 x 32) and z chunk bz; tid is the tile's
 // row in the source plane-pointer table.
-template <int R, Store S, int MODE, int TW>
+template <int R, Store S, int MODE, int TW, bool PQ>
 __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int x0, int y0, int bz, int tid) {
+    static_assert(!PQ || MODE == kPlain || MODE == kDiff, "the gradient modes read float32 p");
     using E = Elem<S>;
     using T = typename E::T;
     using SM = Smem3<R, TW>;
@@ -345,6 +356,7 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
     const T *Pv = (const T *)a.prev;
     T *O = (T *)a.out;
     const float *__restrict__ Pp = a.p;
+    const uint16_t *__restrict__ Pq = a.pq;
 
     // Halo items of the staged plane: 2r rows above/below the tile (TW float4
     // each) and HX4 float4 columns left/right of each tile row.
@@ -424,7 +436,7 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
     using Raw = typename E::Raw;
     struct PlaneRegs {
         Raw front, mv;
-        float4 pv;
+        std::conditional_t<PQ, uint2, float4> pv;   // p as stored
         Raw hv[HPT];      // halo of plane z+R
         float4 br, gp;    // imaging step: bracket and partial gradient of plane z
     };
@@ -435,7 +447,10 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
         r.front = E::ld4raw(U + base + fo);
 #pragma unroll
         for (int k = 0; k < HPT; ++k) r.hv[k] = E::ld4raw(U + hoff[k] + fo);
-        r.pv = ld4nt_f32(Pp + base + zo);
+        if constexpr (PQ)
+            r.pv = ld2nt_u32(Pq + base + zo);
+        else
+            r.pv = ld4nt_f32(Pp + base + zo);
         r.mv = E::ld4ntraw(Pv + base + zo);
         if constexpr (MODE == kImage) {
             r.br = ld4nt_f32(a.img.br_in + base + zo);
@@ -475,6 +490,7 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
 
         if (active) {
             const float4 mvf = E::cvt(cur.mv);
+            const float4 pv = param4(cur.pv, a.pq_base, a.pq_step);
             // x neighbours: 2*HX4+1 float4 chunks of the lane's LDS row
             float xs[4 * (2 * HX4 + 1)];
             const float4 *row = buf + (R + ty) * W4 + HX4 + tx;
@@ -516,10 +532,10 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
                 // consistent
                 static_assert(S != Store::F32, "difference storage is 16-bit");
                 float4 d4;
-                d4.x = update_diff(mvf.x, cur.pv.x, lap[0], src[0], sxy[0] + sz);
-                d4.y = update_diff(mvf.y, cur.pv.y, lap[1], src[1], sxy[1] + sz);
-                d4.z = update_diff(mvf.z, cur.pv.z, lap[2], src[2], sxy[2] + sz);
-                d4.w = update_diff(mvf.w, cur.pv.w, lap[3], src[3], sxy[3] + sz);
+                d4.x = update_diff(mvf.x, pv.x, lap[0], src[0], sxy[0] + sz);
+                d4.y = update_diff(mvf.y, pv.y, lap[1], src[1], sxy[1] + sz);
+                d4.z = update_diff(mvf.z, pv.z, lap[2], src[2], sxy[2] + sz);
+                d4.w = update_diff(mvf.w, pv.w, lap[3], src[3], sxy[3] + sz);
                 asm volatile("" : "+v"(d4.x), "+v"(d4.y), "+v"(d4.z), "+v"(d4.w));
                 draw = E::pack(d4);
                 const float4 ds = E::cvt(draw);
@@ -528,7 +544,7 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    un[i] = update_point(comp(QQ(R), i), comp(mvf, i), comp(cur.pv, i), lap[i], src[i],
+                    un[i] = update_point(comp(QQ(R), i), comp(mvf, i), comp(pv, i), lap[i], src[i],
                                          sxy[i] + sz);
             }
             const long long off = base + (long long)z * plane;
@@ -619,8 +635,9 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
 // SHAPE 0: 64 x 16 tiles over the ntx whole 64-point columns and, beside
 // them, nstrip 32 x 32 tiles for the last, narrower x column (at most 32
 // points), which a 64-point tile would fill to half or less.  Tiles are
-// numbered x fastest, then y, then the strip, then z chunk.
-template <int R, Store S, int MODE, int SHAPE>
+// numbered x fastest, then y, then the strip, then z chunk.  PQ: p is read
+// as 16-bit codes (a.pq) instead of float32.
+template <int R, Store S, int MODE, int SHAPE, bool PQ>
 __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     constexpr int kSmem = SHAPE == 16 ? Smem3<R, 16>::kSize
                           : SHAPE == 8 ? Smem3<R, 8>::kSize
@@ -641,11 +658,12 @@ __global__ __launch_bounds__(kBlock) void k_step3d(const StepArgs a) {
     const int u = t % tiles, bz = t / tiles;
     if constexpr (SHAPE == 0) {
         if (u < nmain)
-            step3d_tile<R, S, MODE, 16>(a, smem, (u % a.ntx) * 64, (u / a.ntx) * 16, bz, u);
+            step3d_tile<R, S, MODE, 16, PQ>(a, smem, (u % a.ntx) * 64, (u / a.ntx) * 16, bz, u);
         else
-            step3d_tile<R, S, MODE, 8>(a, smem, a.ntx * 64, (u - nmain) * 32, bz, u);
+            step3d_tile<R, S, MODE, 8, PQ>(a, smem, a.ntx * 64, (u - nmain) * 32, bz, u);
     } else {
-        step3d_tile<R, S, MODE, SHAPE>(a, smem, (u % a.ntx) * 4 * SHAPE, (u / a.ntx) * (kBlock / SHAPE), bz, u);
+        step3d_tile<R, S, MODE, SHAPE, PQ>(a, smem, (u % a.ntx) * 4 * SHAPE, (u / a.ntx) * (kBlock / SHAPE), bz,
+                                           u);
     }
 }
 
@@ -1394,9 +1412,9 @@ __global__ void k_fill_velocity(const Layout L, const float *vp, int vp_padded, 
     }
 }
 
-__global__ void k_vmax(const Layout L, const float *vel, unsigned *out) {
+__global__ void k_vrange(const Layout L, const float *vel, unsigned *out) {
     const long long n = (long long)L.nx * L.ny * L.nz;
-    float m = 0.f;
+    float m = 0.f, lo = __uint_as_float(0x7F800000u);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % L.nx);
@@ -1406,8 +1424,11 @@ __global__ void k_vmax(const Layout L, const float *vel, unsigned *out) {
         // NaN or non-positive velocities poison the maximum on purpose
         m = (v > 0.f) ? fmaxf(m, v) : __uint_as_float(0x7F800000u);
         if (!(v > 0.f)) break;
+        lo = fminf(lo, v);
     }
+    // positive floats order as their bit patterns
     atomicMax(out, __float_as_uint(m));
+    atomicMin(out + 1, __float_as_uint(lo));
 }
 
 __global__ void k_make_p(const Layout L, const float *vel, double dt2, float *p) {
@@ -1420,6 +1441,28 @@ __global__ void k_make_p(const Layout L, const float *vel, double dt2, float *p)
         const long long o = L.offset(x, y, z);
         const double v = (double)vel[o];
         p[o] = (float)(dt2 * v * v);
+    }
+}
+
+// The 16-bit code of p: the nearest integer in [0, 65535] to (p - base) /
+// step with p = dt^2 v^2, all in float64 (base and step are the float32
+// values the step's decode uses, so the code is the nearest one for that
+// decode).  Each operation rounds on its own (no contraction), as the
+// definition states.
+__global__ void k_make_pq(const Layout L, const float *vel, double dt2, double base, double step,
+                          uint16_t *pq) {
+#pragma clang fp contract(off)
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % L.nx);
+        const int y = (int)((i / L.nx) % L.ny);
+        const int z = (int)(i / ((long long)L.nx * L.ny));
+        const long long o = L.offset(x, y, z);
+        const double v = (double)vel[o];
+        const double p = dt2 * v * v;
+        const double c = step > 0.0 ? rint((p - base) / step) : 0.0;
+        pq[o] = (uint16_t)fmin(fmax(c, 0.0), 65535.0);
     }
 }
 
@@ -1495,12 +1538,13 @@ using StepFn = void (*)(const StepArgs);
 
 template <Store S, int MODE, int... Rs>
 struct Table {
+    template <bool PQ = false>
     static StepFn get3(int r, int shape) {
         StepFn f = nullptr;
-        if (shape == 16) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 16>, 0) : 0), ...);
-        if (shape == 8) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 8>, 0) : 0), ...);
+        if (shape == 16) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 16, PQ>, 0) : 0), ...);
+        if (shape == 8) ((r == Rs ? (f = k_step3d<Rs, S, MODE, 8, PQ>, 0) : 0), ...);
         // (radii 7 and 8 always run 32 x 32 tiles: no mixed kernel)
-        if (shape == 0) ((r == Rs ? (f = k_step3d<Rs, S, MODE, (Rs <= 6 ? 0 : 8)>, 0) : 0), ...);
+        if (shape == 0) ((r == Rs ? (f = k_step3d<Rs, S, MODE, (Rs <= 6 ? 0 : 8), PQ>, 0) : 0), ...);
         return f;
     }
     static StepFn get2(int r) {
@@ -1516,9 +1560,28 @@ StepFn pick(int ndim, int r, int tw4) {
     return ndim == 3 ? Tb::get3(r, tw4) : Tb::get2(r);
 }
 
-// The gradient modes exist for float32 storage only, the difference
-// storage for 16-bit 3D fields only.
-StepFn pick_step(int ndim, int r, Store st, int mode, int tw4) {
+// The gradient modes exist for float32 storage and p only, the difference
+// storage for 16-bit 3D fields only, the 16-bit p codes in 3D only.
+template <Store S, int MODE>
+using Tab = Table<S, MODE, 1, 2, 3, 4, 5, 6, 7, 8>;
+
+StepFn pick_step_pq(int ndim, int r, Store st, int mode, int tw4) {
+    if (ndim != 3 || (mode != kPlain && mode != kDiff)) return nullptr;
+    if (mode == kDiff) {
+        if (st == Store::F16) return Tab<Store::F16, kDiff>::get3<true>(r, tw4);
+        if (st == Store::BF16) return Tab<Store::BF16, kDiff>::get3<true>(r, tw4);
+        return nullptr;
+    }
+    switch (st) {
+        case Store::F32: return Tab<Store::F32, kPlain>::get3<true>(r, tw4);
+        case Store::F16: return Tab<Store::F16, kPlain>::get3<true>(r, tw4);
+        case Store::BF16: return Tab<Store::BF16, kPlain>::get3<true>(r, tw4);
+    }
+    return nullptr;
+}
+
+StepFn pick_step(int ndim, int r, Store st, int mode, int tw4, bool pq) {
+    if (pq) return pick_step_pq(ndim, r, st, mode, tw4);
     if (mode == kBracket) return st == Store::F32 ? pick<Store::F32, kBracket>(ndim, r, tw4) : nullptr;
     if (mode == kImage) return st == Store::F32 ? pick<Store::F32, kImage>(ndim, r, tw4) : nullptr;
     if (mode == kDiff) {
@@ -1573,7 +1636,7 @@ int step_t2_blocks_per_cu(int r) {
 }
 
 hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s) {
-    StepFn f = pick_step(a.L.ndim, a.L.r, st, mode, a.shape3);
+    StepFn f = pick_step(a.L.ndim, a.L.r, st, mode, a.shape3, a.pq != nullptr);
     if (!f) return hipErrorInvalidValue;
     const int tiles = (a.ntx * a.nty + (a.L.ndim == 3 ? a.nstrip : 0)) * a.ntz;
     const int blocks = tiles + a.nsamp_blocks;
@@ -1582,8 +1645,8 @@ hipError_t launch_step(const StepArgs &a, Store st, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
-int step_blocks_per_cu(int ndim, int r, Store st, int mode, int tw4) {
-    StepFn f = pick_step(ndim, r, st, mode, tw4);
+int step_blocks_per_cu(int ndim, int r, Store st, int mode, int tw4, bool pq) {
+    StepFn f = pick_step(ndim, r, st, mode, tw4, pq);
     if (!f) return 0;
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(f), kBlock, 0) !=
@@ -1611,15 +1674,22 @@ hipError_t launch_fill_velocity(const Layout &L, const float *vp, int vp_padded,
     return hipGetLastError();
 }
 
-hipError_t launch_vmax(const Layout &L, const float *vel, unsigned *out_bits, hipStream_t s) {
+hipError_t launch_vrange(const Layout &L, const float *vel, unsigned *out_bits, hipStream_t s) {
     const long long n = (long long)L.nx * L.ny * L.nz;
-    hipLaunchKernelGGL(k_vmax, dim3(grid_for(n)), dim3(kBlock), 0, s, L, vel, out_bits);
+    hipLaunchKernelGGL(k_vrange, dim3(grid_for(n)), dim3(kBlock), 0, s, L, vel, out_bits);
     return hipGetLastError();
 }
 
 hipError_t launch_make_p(const Layout &L, const float *vel, double dt, float *p, hipStream_t s) {
     const long long n = (long long)L.nx * L.ny * L.nz;
     hipLaunchKernelGGL(k_make_p, dim3(grid_for(n)), dim3(kBlock), 0, s, L, vel, dt * dt, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_pq(const Layout &L, const float *vel, double dt, double base, double step,
+                          uint16_t *pq, hipStream_t s) {
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    hipLaunchKernelGGL(k_make_pq, dim3(grid_for(n)), dim3(kBlock), 0, s, L, vel, dt * dt, base, step, pq);
     return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ def _desc(**kw):
     d.storage = kw.get("storage", 0)
     d.tile_x = kw.get("tile_x", 0)
     d.time_block = kw.get("time_block", 0)
+    d.param_storage = kw.get("param", 0)
     return d
 
 
@@ -82,6 +83,12 @@ def test_workspace_bytes_grow_with_grid(lib):
     rc7, b7 = _bytes(lib, _desc(shape=(64, 48, 32), so=10))
     rc8, b8 = _bytes(lib, _desc(shape=(64, 48, 32), so=10, time_block=1))
     assert rc7 == 0 and b7 == b8
+    # 16-bit p codes: the parameter field takes half the bytes; at space
+    # order 2 they rule out two levels per launch, so no extra buffers
+    rc13, b13 = _bytes(lib, _desc(shape=(64, 48, 32), param=_lib.FD_PARAM_Q16))
+    assert rc13 == 0 and b1 - b13 >= 2 * (84 * 68 * 52)
+    rc14, b14 = _bytes(lib, _desc(shape=(64, 48, 32), so=2, param=_lib.FD_PARAM_Q16))
+    assert rc14 == 0 and b14 < b12
 
 
 @pytest.mark.parametrize("bad", [
@@ -90,6 +97,8 @@ def test_workspace_bytes_grow_with_grid(lib):
     dict(time_block=3), dict(time_block=-1), dict(time_block=2, storage=2), dict(time_block=2, so=10),
     dict(time_block=2, ndim=2), dict(storage=3, ndim=2), dict(storage=4, ndim=2), dict(storage=5),
     dict(time_block=2, storage=4),
+    dict(param=2), dict(param=-1), dict(param=1, ndim=2), dict(param=1, time_block=2),
+    dict(param=1, so=2, time_block=2),
 ])
 def test_invalid_descriptors_rejected(lib, bad):
     rc, _ = _bytes(lib, _desc(**bad))

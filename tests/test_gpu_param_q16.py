@@ -1,0 +1,186 @@
+"""16-bit codes of p = dt^2 v^2 (param "q16") against the FP64 oracle.
+
+The codes represent a medium of their own: p' = fma(code, dp, p0) at every
+point.  Run on the velocity v' = sqrt(p') / dt, the oracle steps exactly
+that medium, so a float32 grid with q16 codes must meet the float32 gate
+against it, and every 16-bit storage its usual bar.  The codes are
+computed here from their definition (p0 = dt^2 v_min^2 and dp = (dt^2
+v_max^2 - p0) / 65535 rounded to float32, code = the nearest integer in
+[0, 65535] to (dt^2 v^2 - p0) / dp in float64).  Against the unquantised
+medium the codes are a fixed perturbation of at most dp / 2 per point.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import (assert_field, assert_traces, case, gpu_forward, gpu_grid, need_gpu, oracle_forward,
+                        rel_l2, torch)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def coded_scale(v_pad, dt):
+    """(p0, dp) as float32 values (held in float64)."""
+    v = np.asarray(v_pad, dtype=np.float32).astype(np.float64)
+    dt2 = dt * dt
+    pmin = dt2 * float(v.min()) * float(v.min())
+    pmax = dt2 * float(v.max()) * float(v.max())
+    return float(np.float32(pmin)), float(np.float32((pmax - pmin) / 65535.0))
+
+
+def coded_velocity(v_pad, dt):
+    """The velocity whose dt^2 v^2 is the decoded p' at every point."""
+    v = np.asarray(v_pad, dtype=np.float32).astype(np.float64)
+    p0, dp = coded_scale(v, dt)
+    p = dt * dt * v * v
+    code = np.clip(np.rint((p - p0) / dp), 0, 65535) if dp > 0 else np.zeros_like(p)
+    # code * dp and the sum are exact in 64-bit extended precision (16 + 24
+    # significant bits), so the conversion rounds once, as the fused
+    # multiply-add does
+    exact = code.astype(np.longdouble) * np.longdouble(dp) + np.longdouble(p0)
+    pd = exact.astype(np.float32).astype(np.float64)
+    return np.sqrt(pd) / dt, np.abs(pd - p) / p
+
+
+def oracle_coded(c, residual=None):
+    g = c["og"]
+    vp = oracle.pad_velocity(g, c["v"])
+    vq, _ = coded_velocity(vp, c["dt"])
+    # the damping profile keeps the unquantised v_max, as the grid does
+    sig = oracle.damping(g, oracle.sigma_max_default(g, float(vp.max())))
+    if residual is not None:
+        return oracle.adjoint(g, vq, sig, c["dt"], c["nt"], c["src"], c["rec"], residual)
+    return oracle.forward(g, vq, sig, c["dt"], c["nt"], c["src"], c["wav"].astype(np.float64), c["rec"])
+
+
+@pytest.mark.parametrize("so,tile_x", [(8, 64), (8, 32), (8, 96), (2, 0), (4, 0), (12, 0), (16, 0)])
+def test_float32_fields_on_the_coded_medium(so, tile_x):
+    """float32 wavefields with 16-bit p codes against the oracle on the coded
+    medium, at the float32 gate: every radius, each tile shape, a ragged x
+    column (78 padded points) and two sources."""
+    need_gpu()
+    c = case((70, 33, 26), so, 4, 61, seed=31, nsrc=2, nrec=9)
+    want, u_nt, _, _ = oracle_coded(c)
+    g = gpu_grid(c, tile_x=tile_x, param="q16")
+    dev = torch.device("cuda:0")
+    rec, st = g.forward(c["src"], torch.from_numpy(c["wav"]).to(dev), c["rec"], c["dt"], save_state=True)
+    torch.cuda.synchronize()
+    assert g.time_block == 1
+    p0, dp = coded_scale(oracle.pad_velocity(c["og"], c["v"]), c["dt"])
+    assert g.param_scale() == (p0, dp)
+    assert_traces(rec.cpu().numpy(), want, TOL, "q16 so %d tile %d" % (so, tile_x))
+    assert_field(st[0].cpu().numpy(), u_nt, TOL, "q16 so %d tile %d" % (so, tile_x))
+    g.close()
+
+
+def test_adjoint_on_the_coded_medium():
+    """fd_adjoint with 16-bit p codes against the oracle's adjoint on the
+    coded medium, and the dot test of the coded forward and adjoint."""
+    need_gpu()
+    c = case((48, 37, 30), 8, 5, 70, seed=5, nsrc=2, nrec=8)
+    dev = torch.device("cuda:0")
+    r = np.random.default_rng(1).standard_normal((c["nt"], 8)).astype(np.float32)
+    want, _ = oracle_coded(c, residual=r.astype(np.float64))
+    g = gpu_grid(c, param="q16")
+    got = g.adjoint(c["src"], c["rec"], torch.from_numpy(r).to(dev), c["dt"])
+    wb = c["wav"]
+    Fb = g.forward(c["src"], torch.from_numpy(wb).to(dev), c["rec"], c["dt"])
+    FtFb = g.adjoint(c["src"], c["rec"], Fb, c["dt"])
+    torch.cuda.synchronize()
+    assert_traces(got.cpu().numpy(), want, TOL, "q16 adjoint")
+    fb = Fb.cpu().numpy().astype(np.float64)
+    a1 = float(np.sum(fb * fb))
+    a2 = float(np.sum(wb.astype(np.float64) * FtFb.cpu().numpy()))
+    assert abs(a1 - a2) / abs(a1) <= 1e-6
+    g.close()
+
+
+def test_sixteen_bit_storages_with_codes():
+    """Each 16-bit storage with 16-bit p codes (8 B per point-step, 10 for
+    the difference forms) against the oracle on the coded medium, at the
+    bar of that storage with float32 p; layered medium, so 8, 400 steps."""
+    need_gpu()
+    from paper_1906_10811_amd import Grid
+    shape = (72, 66, 60)
+    cx, cy = (shape[0] - 1) * 5.0, (shape[1] - 1) * 5.0
+    w = synth.workload("layered3d_256", shape=shape, nbl=12, nt=400, src=[(cx + 5.0, cy + 5.0, 20.0)],
+                       rec=synth.line_receivers(40, 0.0, 2 * cx, (cy, 20.0), 3))
+    v = synth.velocity(w)
+    g0 = oracle.Grid(w["shape"], w["spacing"], w["origin"], w["space_order"], w["nbl"])
+    vp = oracle.pad_velocity(g0, v)
+    vq, rel = coded_velocity(vp, w["dt"])
+    sig = oracle.damping(g0, oracle.sigma_max_default(g0, float(vp.max())))
+    wav = synth.wavelets(w)
+    want, *_ = oracle.forward(g0, vq, sig, w["dt"], w["nt"], w["src"], wav.astype(np.float64), w["rec"])
+    plain, *_ = oracle.forward(g0, vp, sig, w["dt"], w["nt"], w["src"], wav.astype(np.float64), w["rec"])
+    dev = torch.device("cuda:0")
+    errs = {}
+    for st in ("f32", "f16", "bf16", "f16_diff", "bf16_diff"):
+        g = Grid(w["shape"], w["spacing"], torch.from_numpy(v).to(dev), space_order=w["space_order"],
+                 nbl=w["nbl"], storage=st, param="q16")
+        rec = g.forward(w["src"], torch.from_numpy(wav).to(dev), w["rec"], w["dt"])
+        torch.cuda.synchronize()
+        errs[st] = rel_l2(rec.cpu().numpy(), want)
+        if st == "f32":
+            errs["f32 vs unquantised"] = rel_l2(rec.cpu().numpy(), plain)
+        g.close()
+    print("q16 codes, max relative p change %.2e;" % rel.max(),
+          "error vs FP64 oracle on the coded medium:", {k: "%.2e" % e for k, e in errs.items()}, flush=True)
+    # p moves by at most dp / 2 plus a float32 rounding: 2^-17 (vmax^2 -
+    # vmin^2) / vmin^2 relative, 6.1e-5 for 1.5-4.5 km/s
+    assert rel.max() <= 2.0 ** -17 * (4.5 ** 2 - 1.5 ** 2) / 1.5 ** 2 + 2.0 ** -24
+    assert errs["f32"] <= TOL
+    assert errs["f16"] <= 5e-3 and errs["bf16"] <= 5e-2
+    assert errs["f16_diff"] <= 1e-3 and errs["bf16_diff"] <= 1e-2
+    # the medium perturbation itself stays far below every 16-bit storage
+    # error (measured 1.1e-5 on this model at 128^3 over 1000 steps)
+    assert errs["f32 vs unquantised"] <= 5e-5
+
+
+def test_codes_through_the_server_and_rejections():
+    """A served request with p codes is bitwise its lone fd_forward run; the
+    gradient refuses the codes."""
+    need_gpu()
+    from paper_1906_10811_amd import Server
+    from paper_1906_10811_amd._lib import FDError
+    c = case((60, 44, 30), 8, 5, 45, seed=19, nsrc=1, nrec=9)
+    alone = {}
+    dev = torch.device("cuda:0")
+    for st in ("f32", "bf16"):
+        g = gpu_grid(c, storage=st, param="q16")
+        _, rec = gpu_forward(c, grid=g)
+        alone[st] = rec.cpu().numpy()
+        if st == "f32":
+            obs = torch.zeros((c["nt"], len(c["rec"])), device=dev)
+            with pytest.raises(FDError):
+                g.gradient(c["src"], torch.from_numpy(c["wav"]).to(dev), c["rec"], obs, c["dt"])
+        g.close()
+    srv = Server(1 << 30, max_slots=2, steps_per_round=7)
+    kw = dict(shape=c["shape"], spacing=c["spacing"], origin=c["origin"], space_order=c["so"], nbl=c["nbl"],
+              vp=c["v"], src_xyz=c["src"], wavelet=c["wav"], rec_xyz=c["rec"], dt=c["dt"])
+    ids = {st: srv.submit(storage=st, param="q16", **kw) for st in alone}
+    for st, rid in ids.items():
+        out, info = srv.wait(rid, timeout=120.0)
+        assert info["status"] == 0
+        assert np.array_equal(out, alone[st]), st
+    srv.close()
+
+
+def test_constant_medium_codes_are_exact():
+    """A constant velocity gives dp = 0: every point decodes to p0, the
+    float32 value of dt^2 v^2, so the traces equal those of float32 p
+    bitwise."""
+    need_gpu()
+    c = case((40, 36, 30), 8, 4, 50, seed=3, nsrc=1, nrec=5, model="const")
+    out = []
+    for param in ("f32", "q16"):
+        g = gpu_grid(c, param=param)
+        _, rec = gpu_forward(c, grid=g)
+        out.append(rec.cpu().numpy())
+        if param == "q16":
+            assert g.param_scale()[1] == 0.0
+        g.close()
+    assert np.array_equal(out[0], out[1])
