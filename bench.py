@@ -308,24 +308,40 @@ def bench_gradient(torch, dev, stream):
     return out
 
 
+def b_alg(storage, param="f32"):
+    """Algorithmic bytes per point-step of the one-step forward: u^n and
+    u^{n-1} (or the difference) read, u^{n+1} written, p read."""
+    field = 4 if storage == "f32" else 2
+    return 3 * field + (field if storage.endswith("_diff") else 0) + (2 if param == "q16" else 4)
+
+
+def _forms(storages):
+    """(key, storage, param) for each storage with float32 p, then each with
+    16-bit p codes."""
+    return [(st, st, "f32") for st in storages] + [(st + "_q16", st, "q16") for st in storages]
+
+
 def bench_precision(torch, dev, stream, ref_rec):
-    """16-bit wavefield storage on layered3d_256: throughput and trace error
-    against the float32 run of the same workload over all 1000 steps (their
-    error against the FP64 oracle is added from the CPU-baseline sample).
-    Returns (results, traces per storage type)."""
+    """16-bit wavefield storage and 16-bit p codes on layered3d_256:
+    throughput and trace error against the float32 run of the same workload
+    over all 1000 steps (their error against the FP64 oracle on the
+    unquantised medium is added from the CPU-baseline sample).  Returns
+    (results, traces per form)."""
     from paper_1906_10811_amd import Grid
     w, v, wav = make_workload("layered3d_256", torch, dev)
     res, recs = {}, {}
     ref = np.asarray(ref_rec, dtype=np.float64)
-    for st, scale in (("bf16", 0.0), ("f16", 0.0), ("bf16_diff", 0.0), ("f16_diff", 0.0)):
-        # f16: automatic power-of-two scale; *_diff: the level and its difference (12 B)
-        g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, amp_scale=scale,
+    forms = [f for f in _forms(("f32", "bf16", "f16", "bf16_diff", "f16_diff")) if f[0] != "f32"]
+    for key, st, param in forms:
+        # f16: automatic power-of-two scale; *_diff: the level and its difference
+        g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, param=param,
                  stream=stream)
         secs, rec = time_forward(torch, g, w, wav, 1, 1, stream)
-        recs[st] = rec.cpu().numpy()
-        err = float(np.linalg.norm(recs[st] - ref) / np.linalg.norm(ref))
-        res[st] = dict(gpts=g.padded_points * w["nt"] / secs / 1e9, rel_l2_vs_f32=err,
-                       b_alg_per_pt=12 if st.endswith("_diff") else 10, amp_scale=scale)
+        recs[key] = rec.cpu().numpy()
+        err = float(np.linalg.norm(recs[key] - ref) / np.linalg.norm(ref))
+        gp = g.padded_points * w["nt"] / secs / 1e9
+        b = b_alg(st, param)
+        res[key] = dict(gpts=gp, rel_l2_vs_f32=err, b_alg_per_pt=b, frac_hbm=round(gp * b / HBM_PEAK_GBS, 4))
         g.close()
     return res, recs
 
@@ -357,9 +373,10 @@ def bench_adjoint(torch, dev, stream):
 def bench_grf512(torch, dev, stream):
     """The precision workload at full size: grf3d_512 (512^3 + 40 damping =
     592^3 padded, Gaussian random field, so 8, 1500 steps), one forward each
-    with FP32, F16 (automatic scale) and BF16 wavefields; 16-bit traces are
-    compared with the FP32 run over all 1500 steps, and every storage type
-    with the FP64 oracle over the first 100 steps (the CPU-baseline slice).
+    with FP32, F16 (automatic scale), BF16 and the two difference storages,
+    and FP32, F16 and BF16 with 16-bit p codes; the other traces are
+    compared with the FP32 run over all 1500 steps, and every form with the
+    FP64 oracle over the first 100 steps (the CPU-baseline slice).
     Returns (results, traces per storage type, (workload, velocity))."""
     from paper_1906_10811_amd import Grid
     w = synth.workload("grf3d_512")
@@ -367,17 +384,20 @@ def bench_grf512(torch, dev, stream):
     v = torch.from_numpy(v_host).to(dev)
     wav = torch.from_numpy(synth.wavelets(w)).to(dev)
     res, recs, ref = {}, {}, None
-    for st in ("f32", "f16", "bf16", "f16_diff", "bf16_diff"):
-        g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, stream=stream)
+    forms = _forms(("f32", "f16", "bf16", "f16_diff", "bf16_diff"))
+    forms = forms[:5] + [f for f in forms[5:] if f[1] in ("f32", "f16", "bf16")]
+    for key, st, param in forms:
+        g = Grid(w["shape"], w["spacing"], v, space_order=8, nbl=w["nbl"], storage=st, param=param,
+                 stream=stream)
         secs, rec = time_forward(torch, g, w, wav, 1, 0, stream)
-        recs[st] = rec.cpu().numpy()
+        recs[key] = rec.cpu().numpy()
         gp = g.padded_points * w["nt"] / secs / 1e9
-        b = B_STEP if st == "f32" else 12.0 if st.endswith("_diff") else 10.0
-        res[st] = dict(gpts=round(gp, 1), frac_hbm=round(gp * b / HBM_PEAK_GBS, 4), b_alg_per_pt=b)
-        if st == "f32":
-            ref = recs[st].astype(np.float64)
+        b = b_alg(st, param)
+        res[key] = dict(gpts=round(gp, 1), frac_hbm=round(gp * b / HBM_PEAK_GBS, 4), b_alg_per_pt=b)
+        if key == "f32":
+            ref = recs[key].astype(np.float64)
         else:
-            res[st]["rel_l2_vs_f32"] = float(np.linalg.norm(recs[st] - ref) / np.linalg.norm(ref))
+            res[key]["rel_l2_vs_f32"] = float(np.linalg.norm(recs[key] - ref) / np.linalg.norm(ref))
         g.close()
     del v
     return res, recs, (w, v_host)
