@@ -109,10 +109,16 @@ template <typename Cvt> struct Elem16 {
     __device__ static float ld(const T *p) { return Cvt::to_f(*p); }
     __device__ static void st(T *p, float v) { *p = Cvt::from_f(v); }
 };
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 struct CvtF16 {
     __device__ static float to_f(uint32_t h) { return h2f((uint16_t)h); }
     __device__ static uint16_t from_f(float f) { return f2h(f); }
-    __device__ static uint32_t pack2(float a, float b) { return (uint32_t)f2h(a) | ((uint32_t)f2h(b) << 16); }
+    // one v_cvt_pk_f16_f32 (round to nearest even, as the single conversion)
+    // instead of two conversions and an or
+    __device__ static uint32_t pack2(float a, float b) {
+        const f32x2 v = {a, b};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+    }
 };
 struct CvtBF16 {
     __device__ static float to_f(uint32_t b) { return b2f((uint16_t)b); }
