@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 B_STEP = 16.0          # algorithmic bytes per point and step, float32 wavefields, one step per launch
 B_STEP2 = 10.0         # ... two leapfrog levels per launch (20 B per point and launch)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_10811_amd", "csrc", f)
-               for f in ("fd_kernels.hip", "fd_internal.h", "fd_api.cpp")]
+               for f in ("fd_kernels.hip", "fd_step3d.h", "fd_step3d_f32.hip", "fd_internal.h", "fd_api.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step3d_so8_layered336.txt")
 
 

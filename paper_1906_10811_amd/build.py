@@ -20,7 +20,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfd.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["fd_kernels.hip"]
+# the 3D step's instantiations are spread over units of similar size that
+# compile in parallel
+HIP_SOURCES = ["fd_kernels.hip", "fd_step3d_f32.hip", "fd_step3d_f16.hip", "fd_step3d_f16_diff.hip",
+               "fd_step3d_bf16.hip", "fd_step3d_bf16_diff.hip"]
 HOST_SOURCES = ["fd_api.cpp", "fd_serve.cpp", "fd_diffusion.cpp", "fd_checkpoint.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -57,7 +60,7 @@ def build(verbose: bool = False) -> str:
         jobs.append([hipcc] + COMMON + ["-x", "hip", "--cuda-host-only", "--offload-arch=" + ARCH, "-c",
                                         os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    with ThreadPoolExecutor(max_workers=min(4, len(jobs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1, len(jobs))) as ex:
         for r in ex.map(_run, jobs):
             if verbose and r.stderr:
                 print(r.stderr, file=sys.stderr)

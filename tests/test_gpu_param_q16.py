@@ -184,3 +184,29 @@ def test_constant_medium_codes_are_exact():
             assert g.param_scale()[1] == 0.0
         g.close()
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_split_runs_with_codes(storage):
+    """33 + 28 steps through save_state / u0 / u_prev equal 61 steps in one
+    run bitwise (the saved levels convert exactly back to the storage
+    type), and a second dt recodes p: a run at dt then at 0.9 dt then at dt
+    again gives the first run's traces bitwise."""
+    need_gpu()
+    c = case((70, 33, 26), 8, 4, 61, seed=11, nsrc=2, nrec=6)
+    dev = torch.device("cuda:0")
+    g = gpu_grid(c, storage=storage, param="q16")
+    wav = torch.from_numpy(c["wav"]).to(dev)
+    full = g.forward(c["src"], wav, c["rec"], c["dt"])
+    ra, st = g.forward(c["src"], wav[:33].contiguous(), c["rec"], c["dt"], save_state=True)
+    rb = g.forward(c["src"], wav[33:].contiguous(), c["rec"], c["dt"], u0=st[0], u_prev=st[1])
+    scale = g.param_scale()
+    other = g.forward(c["src"], wav, c["rec"], 0.9 * c["dt"])
+    assert g.param_scale() != scale
+    again = g.forward(c["src"], wav, c["rec"], c["dt"])
+    torch.cuda.synchronize()
+    assert g.param_scale() == scale
+    assert torch.equal(torch.cat([ra, rb]), full)
+    assert torch.equal(again, full)
+    assert not torch.equal(other, full)
+    g.close()

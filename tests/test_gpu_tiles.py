@@ -29,20 +29,22 @@ def _shapes(c, shapes=(64, 32, 96), **kw):
     return out
 
 
+@pytest.mark.parametrize("param", ["f32", "q16"])
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f16_diff", "bf16_diff"])
 @pytest.mark.parametrize("so", [4, 8, 16])
-def test_forward_bitwise_across_tile_shapes(storage, so):
+def test_forward_bitwise_across_tile_shapes(storage, so, param):
     """80 x 70 x 33 + 6 (92 x 82 x 45 padded): ragged last tiles in x and y
     under every shape, the mixed one with a 28-point strip of 32 x 32
-    tiles; 4 sources, 13 receivers, 50 steps."""
+    tiles; 4 sources, 13 receivers, 50 steps; p in float32 or as 16-bit
+    codes."""
     need_gpu()
     c = case((80, 70, 33), so, 6, 50, seed=40 + so, nsrc=4, nrec=13)
     shapes = (64, 32, 96) if so < 14 else (64, 32)
-    res = _shapes(c, shapes, storage=storage)
+    res = _shapes(c, shapes, storage=storage, param=param)
     (r1, s1) = res[0]
     for tx, (r2, s2) in zip(shapes[1:], res[1:]):
-        print("tiles %s so=%d, %d vs 64: traces equal %d, field equal %d" % (
-            storage, so, tx, int(torch.equal(r1, r2)), int(torch.equal(s1[0], s2[0]))), flush=True)
+        print("tiles %s p %s so=%d, %d vs 64: traces equal %d, field equal %d" % (
+            storage, param, so, tx, int(torch.equal(r1, r2)), int(torch.equal(s1[0], s2[0]))), flush=True)
         assert torch.equal(r1, r2)
         assert torch.equal(s1[0], s2[0]) and torch.equal(s1[1], s2[1])
 
