@@ -410,8 +410,9 @@ __device__ __forceinline__ void step3d_tile(const StepArgs &a, float4 *smem, int
     // queue never moves (the new front takes a free slot); otherwise ROT
     // stays 0 and the entries shift down after each plane, 2R float4 moves.
     // Measured: at so 14 (NQ = 15) rotating is 3.7 % faster; 16-bit fields
-    // at so 10, 12 and 16 gain 2.5-4 % with a padded queue, float32 ones
-    // -1.1 to +0.5 %; at so 8 the nine-fold loop fetched 2.6 % more bytes
+    // at so 10, 12 and 16 gain 1-6 % with a padded queue (at so 4 and 6
+    // they lose up to 1.3 %), float32 ones -1.1 to +0.5 %; at so 8 the
+    // nine-fold loop fetched 2.6 % more bytes
     // from HBM and ran 1.7 % slower (the step is HBM-bound there); in the
     // imaging mode it needs registers that cost a workgroup per CU.
     constexpr int NQ = 2 * R + 1;
