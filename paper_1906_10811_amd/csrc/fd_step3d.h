@@ -3,13 +3,13 @@
 //
 // The step kernel k_step3d<R, S, MODE, SHAPE, PQ> is instantiated for every
 // radius, storage type, step mode, tile shape and form of p; the
-// instantiations of one storage type live in a translation unit of their
-// own (fd_step3d_f32.hip; fd_step3d_f16.hip, fd_step3d_bf16.hip and their
-// _diff forms) so that they compile in parallel, and each exports a lookup
-// of its kernels.  The
-// helpers below (storage types, sampling, source scatter, the update) are
-// also used by the other kernels of fd_kernels.hip.  Everything device-side
-// has internal linkage: each unit compiles its own copy of what it uses.
+// instantiations of one storage type and form live in a translation unit of
+// their own (fd_step3d_f32.hip; fd_step3d_f16.hip, fd_step3d_bf16.hip and
+// their _diff forms) so that they compile in parallel, and each exports a
+// lookup of its kernels.  The helpers below (storage types, sampling,
+// source scatter, the update) are also used by the other kernels of
+// fd_kernels.hip.  Everything device-side has internal linkage: each unit
+// compiles its own copy of what it uses.
 #ifndef FD_STEP3D_H
 #define FD_STEP3D_H
 
