@@ -317,8 +317,8 @@ int fd_checkpoint_schedule(int nt, int slots, fd_ckpt_action *actions, int capac
  * least fd_gradient_workspace_bytes for the same (nt, nrec,
  * checkpoint_every, flags), 256-byte aligned, borrowed for the call's
  * enqueued work.  Errors: FD_ERR_ARG for an unknown flag, a null required
- * pointer or a 16-bit grid; FD_ERR_NOMEM for a short workspace; otherwise
- * as for fd_forward.
+ * pointer, a 16-bit grid or 16-bit p codes (FD_PARAM_Q16); FD_ERR_NOMEM for
+ * a short workspace; otherwise as for fd_forward.
  */
 int fd_gradient(fd_grid *grid, const fd_shot *shot, int nt, double dt,
                 const float *d_obs_dev, int checkpoint_every, int flags,
