@@ -61,6 +61,19 @@ MUTANTS = [
      "c[0] = -2 * sum(c[1:])", "c[0] = -sum(c[1:])"),
     ("weights with alternating sign flipped", PY,
      "c[j] = Fraction(2 * (-1) ** (j + 1) *", "c[j] = Fraction(2 * (-1) ** j *"),
+    ("sinc node window shifted by one", PY,
+     "k0 = int(math.floor(t)) - r + 1", "k0 = int(math.floor(t)) - r + 2"),
+    ("sinc without its Kaiser window", PY,
+     "w.append(sinc * win)", "w.append(sinc * (1.0 if q >= 0.0 else 0.0))"),
+    ("sinc nodes without the layer offset", PY,
+     "ip = k0 + offs[a] + g.nbl", "ip = k0 + offs[a]"),
+    ("sinc nodes outside the grid kept", PY,
+     "            if inside:\n                idx[p_i, ci] = flat\n                w[p_i, ci] = wt",
+     "            if True:\n                idx[p_i, ci] = flat if inside else 0\n                w[p_i, ci] = wt"),
+    ("diffusion step without nu", PY,
+     "u = u + nu * dt * laplacian(g, u)", "u = u + dt * laplacian(g, u)"),
+    ("diffusion stability limit without the factor 2", PY,
+     "return 2.0 / (nu * 4.0 * s_odd", "return 1.0 / (nu * 4.0 * s_odd"),
 ]
 
 
