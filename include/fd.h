@@ -58,7 +58,11 @@
 extern "C" {
 #endif
 
-#define FD_API_VERSION 1
+/* 2: fd_grid_desc gained param_storage and fd_grid_info the parameter
+   fields (appended; zero-initialised descriptors keep the former behaviour,
+   but callers built against version 1 pass the shorter structs and must be
+   rebuilt) */
+#define FD_API_VERSION 2
 
 typedef enum fd_status {
     FD_OK = 0,
